@@ -1,0 +1,260 @@
+"""Reference oracle for CR3BP particle-swarm initial orbit determination.
+
+TEST INFRASTRUCTURE. A plain FP64 CPU implementation (``orc.c``) of what the
+GPU library computes, written from the paper (Zuehlke et al., AAS 22-770,
+arXiv 2207.13175): the CR3BP equations of motion (eqs. cr3bp:x-z), classical
+fixed-step RK4, the azimuth/elevation model and weighted residual cost
+(eqs. rel:pos, meas:function, b:total, total:cost) and Algorithm 1 (PSO).
+
+Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may
+import this package. The GPU library never imports, links or calls it, and it
+imports nothing from the GPU library.
+
+Arrays here are row-major numpy float64: particle states are ``[m, 6]``
+(x, y, z, vx, vy, vz), observation angles ``[K, 2]`` (azimuth, elevation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+COST_PAPER = 0
+COST_CHI2 = 1
+
+
+def build() -> str:
+    """Compile ``orc.c`` into ``liborc.so`` (gcc, FP64, no FP contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [("mu", C.c_double), ("h", C.c_double), ("sigma", C.c_double),
+                ("n_obs", C.c_int32), ("cost_mode", C.c_int32),
+                ("chief", C.c_double * 6),
+                ("t", C.POINTER(C.c_double)), ("angles", C.POINTER(C.c_double))]
+
+
+class _Pso(C.Structure):
+    _fields_ = [("omega", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double),
+                ("seed", C.c_uint64), ("problem", C.c_uint64),
+                ("lo", C.c_double * 6), ("hi", C.c_double * 6)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+_U64 = C.POINTER(C.c_uint64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = C.CDLL(_LIB)
+    lib.orc_rhs.argtypes = [C.c_double, _D, _D]
+    lib.orc_rk4_step.argtypes = [C.c_double, C.c_double, _D]
+    lib.orc_schedule.argtypes = [_D, C.c_int32, C.c_double, _I64, _D]
+    lib.orc_schedule.restype = C.c_int
+    lib.orc_propagate.argtypes = [C.c_double, C.c_double, _D, C.c_int32, _I64, _D, _D]
+    lib.orc_los_angles.argtypes = [_D, _D, _D]
+    lib.orc_predict.argtypes = [C.POINTER(_Problem), _D, _D]
+    lib.orc_predict.restype = C.c_int
+    lib.orc_cost.argtypes = [C.POINTER(_Problem), C.c_int64, _D, _D]
+    lib.orc_cost.restype = C.c_int
+    lib.orc_philox4x64.argtypes = [_U64, _U64, _U64]
+    lib.orc_pso_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Pso), C.c_int64,
+                                 _D, _D, _D, _D, _D, _D, _D, _I64]
+    lib.orc_pso_init.restype = C.c_int
+    lib.orc_pso_iterate.argtypes = [C.POINTER(_Problem), C.POINTER(_Pso), C.c_int64,
+                                    C.c_int64, C.c_int64,
+                                    _D, _D, _D, _D, _D, _D, _D, _I64, _D]
+    lib.orc_pso_iterate.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Problem:
+    """One IOD problem: dynamics, chief state, observation times and angles."""
+
+    def __init__(self, mu, h, sigma, chief, t, angles, cost_mode=COST_PAPER):
+        self.t = _f64(t).ravel()
+        self.angles = _f64(angles, (len(self.t), 2))
+        self.chief = _f64(chief).ravel()
+        self.mu, self.h, self.sigma, self.cost_mode = float(mu), float(h), float(sigma), int(cost_mode)
+        self._s = _Problem(self.mu, self.h, self.sigma, len(self.t), self.cost_mode,
+                           (C.c_double * 6)(*self.chief), _dp(self.t), _dp(self.angles))
+
+    @property
+    def K(self):
+        return len(self.t)
+
+    def with_angles(self, angles):
+        return Problem(self.mu, self.h, self.sigma, self.chief, self.t, angles, self.cost_mode)
+
+
+class Pso:
+    """Algorithm 1 hyper-parameters, Philox identity and initialisation box."""
+
+    def __init__(self, omega, eta1, eta2, seed, lo, hi, problem=0):
+        self.omega, self.eta1, self.eta2 = float(omega), float(eta1), float(eta2)
+        self.seed, self.problem = int(seed), int(problem)
+        self.lo, self.hi = _f64(lo).ravel(), _f64(hi).ravel()
+        self._s = _Pso(self.omega, self.eta1, self.eta2, self.seed, self.problem,
+                       (C.c_double * 6)(*self.lo), (C.c_double * 6)(*self.hi))
+
+
+def rhs(mu, s):
+    lib = _load()
+    s = _f64(s).ravel()
+    f = np.empty(6)
+    lib.orc_rhs(float(mu), _dp(s), _dp(f))
+    return f
+
+
+def rk4_step(mu, h, s):
+    lib = _load()
+    X = _f64(s).ravel().copy()
+    lib.orc_rk4_step(float(mu), float(h), _dp(X))
+    return X
+
+
+def schedule(t, h):
+    lib = _load()
+    t = _f64(t).ravel()
+    ns = np.empty(len(t), dtype=np.int64)
+    tau = np.empty(len(t))
+    rc = lib.orc_schedule(_dp(t), len(t), float(h), ns.ctypes.data_as(_I64), _dp(tau))
+    if rc != 0:
+        raise ValueError("invalid observation schedule")
+    return ns, tau
+
+
+def propagate(mu, h, x0, t):
+    """States [K, 6] of x0 at the observation times t."""
+    lib = _load()
+    ns, tau = schedule(t, h)
+    x0 = _f64(x0).ravel()
+    out = np.empty((len(ns), 6))
+    lib.orc_propagate(float(mu), float(h), _dp(x0), len(ns), ns.ctypes.data_as(_I64),
+                      _dp(tau), _dp(out))
+    return out
+
+
+def los_angles(rho):
+    lib = _load()
+    rho = _f64(rho).ravel()
+    az, el = C.c_double(), C.c_double()
+    lib.orc_los_angles(_dp(rho), C.byref(az), C.byref(el))
+    return az.value, el.value
+
+
+def predict(problem: Problem, x0):
+    """Predicted (azimuth, elevation) [K, 2] of a deputy starting at x0."""
+    lib = _load()
+    x0 = _f64(x0).ravel()
+    out = np.empty((problem.K, 2))
+    if lib.orc_predict(C.byref(problem._s), _dp(x0), _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return out
+
+
+def cost(problem: Problem, x):
+    """Costs [m] of particles x [m, 6]."""
+    lib = _load()
+    x = _f64(x).reshape(-1, 6)
+    out = np.empty(len(x))
+    if lib.orc_cost(C.byref(problem._s), len(x), _dp(x), _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return out
+
+
+def philox4x64(ctr, key):
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.empty(4, dtype=np.uint64)
+    lib.orc_philox4x64(c.ctypes.data_as(_U64), k.ctypes.data_as(_U64), out.ctypes.data_as(_U64))
+    return out
+
+
+class SwarmState:
+    """Oracle swarm: x, v, p [m, 6]; jp, cost [m]; global best g [6], jg, gi."""
+
+    def __init__(self, m):
+        self.m = m
+        self.x = np.zeros((m, 6))
+        self.v = np.zeros((m, 6))
+        self.p = np.zeros((m, 6))
+        self.jp = np.zeros(m)
+        self.cost = np.zeros(m)
+        self.g = np.zeros(6)
+        self.jg = C.c_double(0.0)
+        self.gi = C.c_int64(0)
+        self.iter = 0
+
+    def copy(self):
+        o = SwarmState(self.m)
+        for a in ("x", "v", "p", "jp", "cost", "g"):
+            setattr(o, a, getattr(self, a).copy())
+        o.jg = C.c_double(self.jg.value)
+        o.gi = C.c_int64(self.gi.value)
+        o.iter = self.iter
+        return o
+
+
+def pso_init(problem: Problem, pso: Pso, m: int) -> SwarmState:
+    lib = _load()
+    s = SwarmState(m)
+    rc = lib.orc_pso_init(C.byref(problem._s), C.byref(pso._s), m, _dp(s.x), _dp(s.v),
+                          _dp(s.p), _dp(s.jp), _dp(s.cost), _dp(s.g), C.byref(s.jg),
+                          C.byref(s.gi))
+    if rc != 0:
+        raise ValueError("invalid problem")
+    return s
+
+
+def pso_iterate(problem: Problem, pso: Pso, s: SwarmState, n_count: int):
+    """Advance s by n_count iterations of Algorithm 1; returns the global-best
+    cost after each of them."""
+    lib = _load()
+    hist = np.empty(max(n_count, 1))
+    rc = lib.orc_pso_iterate(C.byref(problem._s), C.byref(pso._s), s.m, s.iter + 1, n_count,
+                             _dp(s.x), _dp(s.v), _dp(s.p), _dp(s.jp), _dp(s.cost), _dp(s.g),
+                             C.byref(s.jg), C.byref(s.gi), _dp(hist))
+    if rc != 0:
+        raise ValueError("invalid problem")
+    s.iter += n_count
+    return hist[:n_count]
+
+
+def pso_solve(problem: Problem, pso: Pso, m: int, n_iter: int):
+    """Full Algorithm 1 run: (best state, best cost, history [n_iter + 1], swarm).
+    history[0] is the global-best cost after initialisation."""
+    s = pso_init(problem, pso, m)
+    h0 = s.jg.value
+    hist = pso_iterate(problem, pso, s, n_iter)
+    return s.g.copy(), s.jg.value, np.concatenate([[h0], hist]), s

@@ -1,0 +1,504 @@
+/*
+ * orc.c -- reference oracle for particle-swarm initial orbit determination in
+ * the circular restricted three-body problem (Zuehlke, Yow, Posada, Nicolich,
+ * Hays, Malik, Henderson, "Initial Orbit Determination for the CR3BP using
+ * Particle Swarm Optimization", AAS 22-770, arXiv 2207.13175).
+ *
+ * TEST INFRASTRUCTURE. This is the plain, slow, obviously-correct CPU
+ * statement of what the GPU library computes. Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it. The GPU library
+ * neither links, includes nor calls it, and the two share no code.
+ *
+ * Precision: IEEE binary64 throughout, round-to-nearest-even. Built with
+ * -ffp-contract=off so that the compiler fuses nothing; every fused
+ * multiply-add below is an explicit C99 fma() (one rounding). sqrt() and the
+ * division operator are correctly rounded. The paper (written in MATLAB) fixes
+ * neither the integrator nor the evaluation order; the order written here is
+ * one fixed choice that the GPU library also follows, because the propagation
+ * is sensitive enough that a different rounding order alone moves the cost far
+ * more than the 1e-11 relative parity bar.
+ *
+ * Paper passages followed (section / equation / algorithm / table):
+ *   - Background, Three-Body Dynamics, eqs. (cr3bp:x), (cr3bp:y), (cr3bp:z):
+ *     the non-dimensional equations of motion in the rotating barycentric frame.
+ *   - Methodology, Particle Swarm Optimizer: relative position eq. (rel:pos),
+ *     line-of-sight unit vector, azimuth/elevation, measurement function
+ *     eq. (meas:function), residual b = y_obs - y, weights w_j = 1/sigma_j^2,
+ *     b_total eq. (b:total) and the scalar cost eq. (total:cost).
+ *   - Algorithm 1 (particle swarm optimisation).
+ * The integrator (classical fixed-step RK4), the angles-only measurement set
+ * and the readings of the garbled passages are stated where they are used.
+ *
+ * Parity pins: every function here is pinned by the CPU tests (closed-form
+ * equilibria, the mu = 0 Kepler circle, h^4 convergence of the Jacobi
+ * constant, mirror and time-reversal symmetry, the paper's printed Jacobi
+ * constants and period ratios, literal-formula angle residuals in extended
+ * precision, noise statistics of the cost, a brute-force grid minimum, the
+ * PSO invariants and isolated velocity-update terms, Philox bit patterns
+ * from numpy).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_COST_PAPER 0
+#define ORC_COST_CHI2 1
+
+/* One observation problem. Times and angles are caller-owned host arrays. */
+typedef struct {
+    double mu;            /* mass parameter mu = mu_m / (mu_m + mu_e) */
+    double h;             /* fixed RK4 step, nondimensional time units */
+    double sigma;         /* angle noise level (rad); weight w = 1/sigma^2 */
+    int32_t n_obs;        /* K */
+    int32_t cost_mode;    /* ORC_COST_PAPER or ORC_COST_CHI2 */
+    double chief[6];      /* chief state at t = 0 */
+    const double *t;      /* [K] observation times, t_0 = 0 is the epoch */
+    const double *angles; /* [K][2] observed (azimuth, elevation), rad */
+} orc_problem;
+
+/* Swarm hyper-parameters of Algorithm 1 plus the random-stream identity. */
+typedef struct {
+    double omega;      /* inertia */
+    double eta1;       /* cognitive (self-confidence) weight */
+    double eta2;       /* social (swarm-confidence) weight */
+    uint64_t seed;     /* Philox key word 0 */
+    uint64_t problem;  /* Philox counter word 2 (problem index in a batch) */
+    double lo[6];      /* initialisation box, absolute */
+    double hi[6];
+} orc_pso;
+
+/* ------------------------------------------------------------------------ */
+/* Dynamics: eqs. (cr3bp:x)-(cr3bp:z).                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Right-hand side of the CR3BP in the rotating barycentric frame:
+ *   xdd =  2 yd + x - (1-mu)(x+mu)/r1^3 - mu (x-(1-mu))/r2^3
+ *   ydd = -2 xd + y - (1-mu) y/r1^3     - mu y/r2^3
+ *   zdd =           - (1-mu) z/r1^3     - mu z/r2^3
+ * with r1 the distance to the larger primary at (-mu,0,0) and r2 to the
+ * smaller at (1-mu,0,0). (The paper's y equation writes "mu" without the
+ * backslash in r1; it is the same mu.) The common factor (1-mu)/r1^3 + mu/r2^3
+ * of the y and z terms is formed once. */
+void orc_rhs(double mu, const double s[6], double f[6])
+{
+    const double mu1 = 1.0 - mu;
+    const double x = s[0], y = s[1], z = s[2];
+    const double vx = s[3], vy = s[4];
+    const double d1 = x + mu;            /* x - (-mu) */
+    const double d2 = x - mu1;           /* x - (1-mu) */
+    const double q = fma(z, z, y * y);   /* y^2 + z^2 */
+    const double r1s = fma(d1, d1, q);   /* r1^2 */
+    const double r2s = fma(d2, d2, q);   /* r2^2 */
+    const double c1 = mu1 / (r1s * sqrt(r1s));  /* (1-mu)/r1^3 */
+    const double c2 = mu / (r2s * sqrt(r2s));   /* mu/r2^3 */
+    const double cs = c1 + c2;
+    f[0] = s[3];
+    f[1] = s[4];
+    f[2] = s[5];
+    f[3] = fma(-c2, d2, fma(-c1, d1, fma(2.0, vy, x)));
+    f[4] = fma(-cs, y, fma(-2.0, vx, y));
+    f[5] = -(cs * z);
+}
+
+/* One classical fourth-order Runge-Kutta step of size h, in place:
+ *   k1 = f(X), k2 = f(X + h/2 k1), k3 = f(X + h/2 k2), k4 = f(X + h k3),
+ *   X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4).
+ * The paper does not name its propagator; fixed-step RK4 is the reading. */
+void orc_rk4_step(double mu, double h, double X[6])
+{
+    const double h2 = 0.5 * h;
+    const double h6 = h / 6.0;
+    double k1[6], k2[6], k3[6], k4[6], s[6];
+    int d;
+    orc_rhs(mu, X, k1);
+    for (d = 0; d < 6; d++) s[d] = fma(h2, k1[d], X[d]);
+    orc_rhs(mu, s, k2);
+    for (d = 0; d < 6; d++) s[d] = fma(h2, k2[d], X[d]);
+    orc_rhs(mu, s, k3);
+    for (d = 0; d < 6; d++) s[d] = fma(h, k3[d], X[d]);
+    orc_rhs(mu, s, k4);
+    for (d = 0; d < 6; d++) {
+        double a = fma(2.0, k2[d], k1[d]);
+        a = fma(2.0, k3[d], a);
+        a = a + k4[d];
+        X[d] = fma(h6, a, X[d]);
+    }
+}
+
+/* Observation schedule on the fixed grid t = j h. An observation time within
+ * 1e-9 h of a grid point is taken after that many whole steps (tau = 0).
+ * Otherwise it is taken from a side copy of the state after floor(t/h) steps,
+ * advanced by one partial step tau = t - floor(t/h) h; the main trajectory
+ * stays on the grid. Returns 0, or -1 if the times are negative, non-finite
+ * or not strictly increasing, or h is not positive and finite. */
+int orc_schedule(const double *t, int32_t n_obs, double h, int64_t *nsteps, double *tau)
+{
+    int32_t k;
+    if (!(h > 0.0) || !isfinite(h) || n_obs < 1) return -1;
+    for (k = 0; k < n_obs; k++) {
+        double q, tk = t[k];
+        int64_t nn;
+        if (!isfinite(tk) || tk < 0.0) return -1;
+        if (k > 0 && !(tk > t[k - 1])) return -1;
+        q = tk / h;
+        if (q > 9.0e15) return -1;
+        nn = (int64_t)floor(q + 0.5);
+        if (fabs(tk - (double)nn * h) <= 1e-9 * h) {
+            nsteps[k] = nn;
+            tau[k] = 0.0;
+        } else {
+            nn = (int64_t)floor(q);
+            nsteps[k] = nn;
+            tau[k] = tk - (double)nn * h;
+        }
+    }
+    return 0;
+}
+
+/* Propagate x0 to every observation time; out is [K][6]. */
+void orc_propagate(double mu, double h, const double x0[6], int32_t n_obs,
+                   const int64_t *nsteps, const double *tau, double *out)
+{
+    double X[6];
+    int64_t step = 0;
+    int32_t k;
+    memcpy(X, x0, sizeof X);
+    for (k = 0; k < n_obs; k++) {
+        double S[6];
+        while (step < nsteps[k]) {
+            orc_rk4_step(mu, h, X);
+            step++;
+        }
+        memcpy(S, X, sizeof S);
+        if (tau[k] != 0.0) orc_rk4_step(mu, tau[k], S);
+        memcpy(out + 6 * (int64_t)k, S, sizeof S);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Measurement model: eq. (rel:pos), the LOS vector, azimuth and elevation.  */
+/* ------------------------------------------------------------------------ */
+
+/* Predicted angles for a relative position rho = r_deputy - r_chief, written
+ * as the paper defines them: L = rho/|rho|, azimuth = atan2(L_y, L_x) (the
+ * paper prints a one-argument atan2 of L(2)/L(1); the four-quadrant form is
+ * the reading), elevation = asin(L_z). All components are in the rotating
+ * frame. A zero rho has no line of sight: both angles are NaN. */
+void orc_los_angles(const double rho[3], double *az, double *el)
+{
+    const double r = sqrt(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
+    if (r == 0.0) {
+        *az = NAN;
+        *el = NAN;
+        return;
+    }
+    *az = atan2(rho[1] / r, rho[0] / r);
+    *el = asin(rho[2] / r);
+}
+
+/* Chief positions at the observation times; rc is [K][3]. The chief state is
+ * known (Methodology, Deputy Chief Scenario) and propagated with the same
+ * integrator and schedule as the particles. */
+static void chief_positions(const orc_problem *P, const int64_t *ns, const double *tau, double *rc)
+{
+    double *st = (double *)malloc(sizeof(double) * 6 * (size_t)P->n_obs);
+    int32_t k;
+    orc_propagate(P->mu, P->h, P->chief, P->n_obs, ns, tau, st);
+    for (k = 0; k < P->n_obs; k++) {
+        rc[3 * k + 0] = st[6 * k + 0];
+        rc[3 * k + 1] = st[6 * k + 1];
+        rc[3 * k + 2] = st[6 * k + 2];
+    }
+    free(st);
+}
+
+/* Predicted (azimuth, elevation) of a deputy starting at x0, at every
+ * observation time; out is [K][2]. Used to simulate observations. */
+int orc_predict(const orc_problem *P, const double x0[6], double *out)
+{
+    const int32_t K = P->n_obs;
+    int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)K);
+    double *rc = (double *)malloc(sizeof(double) * 3 * (size_t)K);
+    double *st = (double *)malloc(sizeof(double) * 6 * (size_t)K);
+    int32_t k;
+    int rc_ok = orc_schedule(P->t, K, P->h, ns, tau);
+    if (rc_ok == 0) {
+        chief_positions(P, ns, tau, rc);
+        orc_propagate(P->mu, P->h, x0, K, ns, tau, st);
+        for (k = 0; k < K; k++) {
+            double rho[3];
+            rho[0] = st[6 * k + 0] - rc[3 * k + 0];
+            rho[1] = st[6 * k + 1] - rc[3 * k + 1];
+            rho[2] = st[6 * k + 2] - rc[3 * k + 2];
+            orc_los_angles(rho, &out[2 * k], &out[2 * k + 1]);
+        }
+    }
+    free(ns); free(tau); free(rc); free(st);
+    return rc_ok;
+}
+
+/* Residual angles b = y_obs - y for one observation (azimuth wrapped to
+ * (-pi, pi]), evaluated through the angle-difference identities
+ *   sin(a_obs - a) |rho_xy| = sin a_obs rho_x - cos a_obs rho_y
+ *   cos(a_obs - a) |rho_xy| = cos a_obs rho_x + sin a_obs rho_y
+ * (and likewise for the elevation with (|rho_xy|, rho_z)), so that atan2 is
+ * applied to the residual itself: any one-ulp difference between atan2
+ * implementations is then relative to the residual, not to the angle.
+ * Mathematically this equals wrap(a_obs - atan2(L_y, L_x)) and
+ * b_obs - asin(L_z). When rho_xy = 0 the azimuth is atan2(0, 0) = 0, so the
+ * azimuth residual is wrap(a_obs). Returns 0, or 1 if rho = 0 (no line of
+ * sight). */
+static int residual(const double rho[3], double sa, double ca, double sb, double cb,
+                    double *da, double *db)
+{
+    const double rx = rho[0], ry = rho[1], rz = rho[2];
+    double rxy, na, nd;
+    if (rx == 0.0 && ry == 0.0 && rz == 0.0) return 1;
+    rxy = sqrt(fma(rx, rx, ry * ry));
+    if (rxy == 0.0) {
+        na = sa;
+        nd = ca;
+    } else {
+        na = fma(sa, rx, -(ca * ry));
+        nd = fma(ca, rx, sa * ry);
+    }
+    *da = atan2(na, nd);
+    *db = atan2(fma(sb, rxy, -(cb * rz)), fma(cb, rxy, sb * rz));
+    return 0;
+}
+
+/* Internal per-problem tables shared by every particle of one evaluation. */
+typedef struct {
+    int64_t *ns;
+    double *tau, *rc, *sa, *ca, *sb, *cb;
+    double w;
+} tables;
+
+static int tables_make(const orc_problem *P, tables *T)
+{
+    const int32_t K = P->n_obs;
+    int32_t k;
+    T->ns = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    T->tau = (double *)malloc(sizeof(double) * (size_t)K);
+    T->rc = (double *)malloc(sizeof(double) * 3 * (size_t)K);
+    T->sa = (double *)malloc(sizeof(double) * (size_t)K);
+    T->ca = (double *)malloc(sizeof(double) * (size_t)K);
+    T->sb = (double *)malloc(sizeof(double) * (size_t)K);
+    T->cb = (double *)malloc(sizeof(double) * (size_t)K);
+    if (orc_schedule(P->t, K, P->h, T->ns, T->tau) != 0) return -1;
+    chief_positions(P, T->ns, T->tau, T->rc);
+    for (k = 0; k < K; k++) {
+        T->sa[k] = sin(P->angles[2 * k]);
+        T->ca[k] = cos(P->angles[2 * k]);
+        T->sb[k] = sin(P->angles[2 * k + 1]);
+        T->cb[k] = cos(P->angles[2 * k + 1]);
+    }
+    /* weights w_j = 1/sigma_j^2 with one sigma for both angles */
+    T->w = 1.0 / (P->sigma * P->sigma);
+    return 0;
+}
+
+static void tables_free(tables *T)
+{
+    free(T->ns); free(T->tau); free(T->rc);
+    free(T->sa); free(T->ca); free(T->sb); free(T->cb);
+}
+
+/* Cost J of one particle, eqs. (b:total) and (total:cost): per observation
+ * e_k = b_k^T W b_k = w (da^2 + db^2); b_total = [e_1 ... e_K] is a row
+ * vector and "the square of the row vector" is read as its inner product,
+ * J = sum_k e_k^2 (PAPER mode). CHI2 mode is J = sum_k e_k. Accumulated in
+ * ascending k from +0. A zero line of sight makes e_k = +inf. */
+static double cost_one(const orc_problem *P, const tables *T, const double x0[6])
+{
+    double X[6];
+    double J = 0.0;
+    int64_t step = 0;
+    int32_t k;
+    memcpy(X, x0, sizeof X);
+    for (k = 0; k < P->n_obs; k++) {
+        double S[6], rho[3], da, db, e;
+        while (step < T->ns[k]) {
+            orc_rk4_step(P->mu, P->h, X);
+            step++;
+        }
+        memcpy(S, X, sizeof S);
+        if (T->tau[k] != 0.0) orc_rk4_step(P->mu, T->tau[k], S);
+        rho[0] = S[0] - T->rc[3 * k + 0];
+        rho[1] = S[1] - T->rc[3 * k + 1];
+        rho[2] = S[2] - T->rc[3 * k + 2];
+        if (residual(rho, T->sa[k], T->ca[k], T->sb[k], T->cb[k], &da, &db) != 0)
+            e = INFINITY;
+        else
+            e = T->w * fma(da, da, db * db);
+        if (P->cost_mode == ORC_COST_CHI2)
+            J = J + e;
+        else
+            J = fma(e, e, J);
+    }
+    return J;
+}
+
+/* Costs of m particles; x is [m][6]. */
+int orc_cost(const orc_problem *P, int64_t m, const double *x, double *cost)
+{
+    tables T;
+    int64_t i;
+    if (tables_make(P, &T) != 0) {
+        tables_free(&T);
+        return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i = 0; i < m; i++) cost[i] = cost_one(P, &T, x + 6 * i);
+    tables_free(&T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel     */
+/* random numbers: as easy as 1, 2, 3", SC'11).                              */
+/* ------------------------------------------------------------------------ */
+
+static void mul128(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+/* Ten rounds; the key is bumped by the Weyl constants before every round
+ * after the first. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    int r;
+    for (r = 0; r < 10; r++) {
+        uint64_t hi0, lo0, hi1, lo1;
+        if (r > 0) {
+            k0 += 0x9E3779B97F4A7C15ULL;
+            k1 += 0xBB67AE8584CAA73BULL;
+        }
+        mul128(0xD2E7470EE14C6C93ULL, c0, &hi0, &lo0);
+        mul128(0xCA5A826395121157ULL, c2, &hi1, &lo1);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform double in [0,1) from the top 53 bits of a word. */
+static double u01(uint64_t w)
+{
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle swarm optimisation: Algorithm 1.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Ordering key for costs: NaN is never selected, so it ranks as +inf. */
+static double key(double J)
+{
+    return isnan(J) ? INFINITY : J;
+}
+
+/* Lowest index with the smallest key. */
+static int64_t argmin(int64_t m, const double *jp)
+{
+    int64_t i, best = 0;
+    for (i = 1; i < m; i++)
+        if (key(jp[i]) < key(jp[best])) best = i;
+    return best;
+}
+
+/* Algorithm 1, initialisation: particle states uniform in the box
+ * (x = lo + (hi - lo) u, u from Philox counter (b, i, problem, 0) where block
+ * b = 0 gives dimensions 0-3 and b = 1 dimensions 4-5), velocities zero,
+ * personal bests equal to the initial states, global best the lowest-cost
+ * particle. Arrays are [m][6] (x, v, p) and [m] (jp, cost). g receives the
+ * global-best state, *jg its cost key and *gi the particle index. */
+int orc_pso_init(const orc_problem *P, const orc_pso *S, int64_t m,
+                 double *x, double *v, double *p, double *jp, double *cost,
+                 double g[6], double *jg, int64_t *gi)
+{
+    const uint64_t key2[2] = {S->seed, 0};
+    int64_t i;
+    int d;
+    if (m < 1) return -1;
+    for (i = 0; i < m; i++) {
+        uint64_t c[4], u[8];
+        c[0] = 0; c[1] = (uint64_t)i; c[2] = S->problem; c[3] = 0;
+        orc_philox4x64(c, key2, u);
+        c[0] = 1;
+        orc_philox4x64(c, key2, u + 4);
+        for (d = 0; d < 6; d++) {
+            x[6 * i + d] = S->lo[d] + (S->hi[d] - S->lo[d]) * u01(u[d]);
+            v[6 * i + d] = 0.0;
+        }
+    }
+    if (orc_cost(P, m, x, cost) != 0) return -1;
+    for (i = 0; i < m; i++) {
+        for (d = 0; d < 6; d++) p[6 * i + d] = x[6 * i + d];
+        jp[i] = cost[i];
+    }
+    *gi = argmin(m, jp);
+    *jg = key(jp[*gi]);
+    for (d = 0; d < 6; d++) g[d] = p[6 * *gi + d];
+    return 0;
+}
+
+/* Algorithm 1, iterations n = n_first .. n_first + n_count - 1 (n counts from
+ * 1). For each particle: evaluate the current state (at n = 1 the
+ * initialisation's cost of the same state is reused), keep it as the personal
+ * best if strictly lower (NaN ranks as +inf), draw r1, r2 (Philox counter (n, i, problem, 1),
+ * words 0 and 1), then
+ *   v <- omega v + eta1 r1 (p - x) + eta2 r2 (g - x),   x <- x + v,
+ * using the global best g of the previous iteration. After the whole swarm:
+ * if the lowest personal-best cost is strictly below the global-best cost,
+ * the global best moves to that personal best. hist (may be NULL) receives
+ * the global-best cost after each iteration. */
+int orc_pso_iterate(const orc_problem *P, const orc_pso *S, int64_t m,
+                    int64_t n_first, int64_t n_count,
+                    double *x, double *v, double *p, double *jp, double *cost,
+                    double g[6], double *jg, int64_t *gi, double *hist)
+{
+    const uint64_t key2[2] = {S->seed, 0};
+    int64_t n, i;
+    int d;
+    if (m < 1 || n_first < 1 || n_count < 0) return -1;
+    for (n = n_first; n < n_first + n_count; n++) {
+        int64_t b;
+        if (n >= 2 && orc_cost(P, m, x, cost) != 0) return -1;
+        for (i = 0; i < m; i++) {
+            uint64_t c[4], u[4];
+            double a1, a2;
+            if (key(cost[i]) < key(jp[i])) {
+                jp[i] = cost[i];
+                for (d = 0; d < 6; d++) p[6 * i + d] = x[6 * i + d];
+            }
+            c[0] = (uint64_t)n; c[1] = (uint64_t)i; c[2] = S->problem; c[3] = 1;
+            orc_philox4x64(c, key2, u);
+            a1 = S->eta1 * u01(u[0]);
+            a2 = S->eta2 * u01(u[1]);
+            for (d = 0; d < 6; d++) {
+                double xi = x[6 * i + d];
+                double vi = S->omega * v[6 * i + d] + a1 * (p[6 * i + d] - xi) + a2 * (g[d] - xi);
+                v[6 * i + d] = vi;
+                x[6 * i + d] = xi + vi;
+            }
+        }
+        b = argmin(m, jp);
+        if (key(jp[b]) < *jg) {
+            *jg = key(jp[b]);
+            *gi = b;
+            for (d = 0; d < 6; d++) g[d] = p[6 * b + d];
+        }
+        if (hist) hist[n - n_first] = *jg;
+    }
+    return 0;
+}

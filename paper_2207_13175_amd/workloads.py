@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs for CR3BP particle-swarm IOD workloads.
+
+This module only draws numbers: chief and deputy initial states, observation
+times, measurement noise, swarm boxes and hyper-parameters. It holds none of
+the method's arithmetic (no propagation, no angles, no cost), so both the GPU
+library's callers and the reference oracle's tests can use it. Observed
+angles are made by the caller as ``predict(truth) + noise``.
+
+The recipes mirror the paper's deputy-chief scenario (Methodology, Deputy
+Chief Scenario; Results): a known chief near the Earth-Moon L1/L2 region, a
+deputy a small offset away, evenly spaced azimuth/elevation observations with
+Gaussian angle noise, and a swarm initialised in a feasible box around the
+chief (Algorithm 1 with bounded initialisation). Everything is
+nondimensional (LU, TU) with the Earth-Moon mass parameter below.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MU_EARTH_MOON = 0.012150585
+C0_CHIEF = np.array([1.15, 0.0, 0.05, 0.0, 0.2, 0.0])
+
+
+@dataclass
+class Workload:
+    """One IOD problem plus the swarm that solves it."""
+    name: str
+    mu: float
+    h: float
+    sigma: float
+    chief: np.ndarray          # [6] chief state at t = 0
+    truth: np.ndarray          # [6] true deputy state at t = 0
+    t: np.ndarray              # [K] observation times (t = 0 is the epoch)
+    noise: np.ndarray          # [K, 2] N(0, sigma^2) draws for (azimuth, elevation)
+    m: int                     # particles
+    n_iter: int                # PSO iterations N
+    omega: float = 0.7
+    eta1: float = 1.5
+    eta2: float = 1.5
+    pso_seed: int = 0
+    lo: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    hi: np.ndarray = field(default_factory=lambda: np.zeros(6))
+
+    @property
+    def K(self) -> int:
+        return len(self.t)
+
+    def particle_steps(self, nsteps_last: int) -> int:
+        """RK4 particle-steps of one full solve: N*m evaluations (the first
+        iteration reuses the initial evaluation) of nsteps_last steps each."""
+        return int(self.n_iter) * int(self.m) * int(nsteps_last)
+
+
+def uniform_ball(rng: np.random.Generator, radius: float) -> np.ndarray:
+    """Point uniform in volume in a 3-ball."""
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    return d * radius * rng.random() ** (1.0 / 3.0)
+
+
+def even_times(T: float, K: int) -> np.ndarray:
+    """K observation times evenly over (0, T]: t_k = k T / K, k = 1..K."""
+    return np.arange(1, K + 1, dtype=np.float64) * T / K
+
+
+def c0(seed: int = 0, sigma: float = 1e-5) -> Workload:
+    """Small case: m = 256 particles, N = 100 iterations, 10 observations over
+    0.5 TU, h = 1e-3; deputy = chief + ball(1e-3) position offset + cube
+    (+-1e-3) velocity offset; box chief +- 2e-3 in every dimension."""
+    rng = np.random.default_rng([seed, 0])
+    chief = C0_CHIEF.copy()
+    truth = chief.copy()
+    truth[:3] += uniform_ball(rng, 1e-3)
+    truth[3:] += rng.uniform(-1e-3, 1e-3, 3)
+    t = even_times(0.5, 10)
+    noise = rng.standard_normal((10, 2)) * sigma
+    return Workload("c0_m256_K10_T0.5_h1e-3_N100", MU_EARTH_MOON, 1e-3, sigma, chief, truth, t,
+                    noise, 256, 100, pso_seed=seed, lo=chief - 2e-3, hi=chief + 2e-3)
+
+
+def c1(seed: int = 0, sigma: float = 1e-5, m: int = 65536, n_iter: int = 200) -> Workload:
+    """Single large swarm: chief = c0 chief + U(+-0.02) per component; deputy
+    offsets up to 5e-3 (ball) / 5e-3 (cube); 40 observations over 2.0 TU;
+    h = 5e-4 (4000 steps); box chief +- 1e-2; 65,536 particles x 200 iterations."""
+    rng = np.random.default_rng([seed, 1])
+    chief = C0_CHIEF + rng.uniform(-0.02, 0.02, 6)
+    truth = chief.copy()
+    truth[:3] += uniform_ball(rng, 5e-3)
+    truth[3:] += rng.uniform(-5e-3, 5e-3, 3)
+    t = even_times(2.0, 40)
+    noise = rng.standard_normal((40, 2)) * sigma
+    return Workload(f"c1_m{m}_K40_T2.0_h5e-4_N{n_iter}", MU_EARTH_MOON, 5e-4, sigma, chief,
+                    truth, t, noise, m, n_iter, pso_seed=seed, lo=chief - 1e-2, hi=chief + 1e-2)
+
+
+def tiny(seed: int = 0, K: int = 3, T: float = 0.1, h: float = 1e-3, m: int = 64,
+         n_iter: int = 20, sigma: float = 1e-5) -> Workload:
+    """Tiny problem for brute-force and edge-case checks."""
+    rng = np.random.default_rng([seed, 2])
+    chief = C0_CHIEF.copy()
+    truth = chief.copy()
+    truth[:3] += uniform_ball(rng, 1e-3)
+    truth[3:] += rng.uniform(-1e-3, 1e-3, 3)
+    t = even_times(T, K)
+    noise = rng.standard_normal((K, 2)) * sigma
+    return Workload(f"tiny_K{K}", MU_EARTH_MOON, h, sigma, chief, truth, t, noise, m, n_iter,
+                    pso_seed=seed, lo=chief - 2e-3, hi=chief + 2e-3)
+
+
+def random_swarm(seed: int, m: int, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """[m, 6] particle states uniform in the box (test inputs, numpy PCG64)."""
+    rng = np.random.default_rng([seed, 3])
+    return lo + (hi - lo) * rng.random((m, 6))
