@@ -1,0 +1,212 @@
+"""Benchmark: FP64 particle-swarm IOD in the CR3BP on one MI355X.
+
+One step = one whole solve of the single-large-swarm workload through the C
+ABI: swarm initialisation (Philox box init + first fitness evaluation), 200
+iterations of Algorithm 1 (fitness = RK4 over 4000 steps to 40 observations,
+azimuth/elevation residual cost, personal best, Philox velocity/position
+update, global-best reduction) and the final global-best read-back. Inputs
+(chief, truth, observation noise) are seeded and synthetic; the observed
+angles are the library's own prediction for the true deputy plus noise.
+
+Prints one JSON line. ``value`` is particle-RK4-steps/s of whole solves with
+inputs resident in HBM. ``roofline`` covers the dominant kernel (the fused
+iteration kernel): algorithmic FP64 flop-equivalents per launch divided by
+its average launch time, measured with HIP events on the launch stream.
+``cpu_baseline`` times the reference oracle on a bounded sample of the same
+fitness work on the host cores (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("particle·RK4-steps/s (FP64, FP32) + % vector peak; "
+          "batched IOD solves/s at fixed error")
+UNIT = "particle·RK4-steps/s"
+
+# Algorithmic work (flop-equivalents; sqrt, division and atan2 count one each)
+FLOP_PER_STEP = 186      # RK4 step: 170 flops + 8 sqrt + 8 div
+FLOP_PER_OBS = 27        # residual and cost: 24 flops + 1 sqrt + 2 atan2
+FLOP_PER_UPDATE = 50     # PSO velocity/position update of one particle
+PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_13175_amd", "csrc", "iod_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the iteration kernel from the committed
+    rocprofv3 counter summary, or None if the kernel changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_workload(name):
+    from paper_2207_13175_amd import workloads as W
+    if name == "c1":
+        return W.c1(0)
+    if name == "c0":
+        return W.c0(0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def observed_angles(iod, torch, wl):
+    """Truth prediction by the library (placeholder angles) plus the seeded noise."""
+    h0 = iod.iod_create(wl.mu, wl.chief, wl.t, np.zeros((wl.K, 2)), wl.sigma, h=wl.h)
+    x = torch.zeros((6, 64), dtype=torch.float64, device="cuda")
+    x[:, 0] = torch.from_numpy(wl.truth).cuda()
+    ang = torch.zeros((wl.K, 2, 64), dtype=torch.float64, device="cuda")
+    iod.iod_predict(h0, x, 1, ang)
+    torch.cuda.synchronize()
+    iod.iod_destroy(h0)
+    return ang[:, :, 0].cpu().numpy() + wl.noise
+
+
+def cpu_baseline(wl, obs, target_s):
+    """Oracle fitness on chunks of the workload's particles until target_s."""
+    import oracle
+    from paper_2207_13175_amd import workloads as W
+    P = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, obs)
+    ns, _ = oracle.schedule(wl.t, wl.h)
+    chunk = 1024
+    xs = W.random_swarm(0, 64 * chunk, wl.lo, wl.hi)
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.cost(P, xs[done % len(xs):done % len(xs) + chunk])
+        done += chunk
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    steps = done * int(ns[-1])
+    return {"value": steps / el, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{done} particle fitness evaluations of the {wl.name} problem "
+                      f"({int(ns[-1])} RK4 steps + {wl.K} observations each), "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2207_13175_amd as iod
+    from paper_2207_13175_amd import __name__ as _pkg  # noqa: F401
+
+    if not os.path.exists(iod.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    wl = make_workload(args.workload)
+    if args.iters is not None:
+        wl.n_iter = args.iters
+    obs = observed_angles(iod, torch, wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    ns, _ = iod.iod_schedule(wl.t, wl.h)
+    steps_per_eval = int(ns[-1])
+    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    sw = iod.Swarm(wl.m, device="cuda", hist_len=wl.n_iter + 1)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def solve(events=None):
+        iod.iod_swarm_init(h, sw, params, stream)
+        if events is None:
+            iod.iod_step(h, sw, params, wl.n_iter, stream)
+        else:
+            for n in range(wl.n_iter):
+                events[n][0].record(stream)
+                iod.iod_step(h, sw, params, 1, stream)
+                events[n][1].record(stream)
+        return iod.iod_swarm_best(h, sw, stream)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(wl.n_iter)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best = None
+    for k in range(args.steps):
+        best = solve(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    launch_ms = [e0.elapsed_time(e1) for row in evs for (e0, e1) in row]
+    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    # average algorithmic work of one iteration-kernel launch: every launch
+    # updates m particles, all but the first iteration also evaluate them
+    flop_eval = steps_per_eval * FLOP_PER_STEP + wl.K * FLOP_PER_OBS
+    flop_launch = wl.m * ((wl.n_iter - 1) / wl.n_iter * flop_eval + FLOP_PER_UPDATE)
+    achieved = flop_launch / avg_launch_s / 1e12
+    ps_per_solve = wl.particle_steps(steps_per_eval)
+    value = args.steps * ps_per_solve / elapsed
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "particles": wl.m, "iterations": wl.n_iter,
+                   "observations": wl.K, "arc_tu": float(wl.t[-1]), "h": wl.h,
+                   "rk4_steps_per_eval": steps_per_eval,
+                   "particle_steps_per_solve": ps_per_solve,
+                   "solves_per_s": args.steps / elapsed,
+                   "gbest_cost": best[1], "gbest_pos_err_lu":
+                       float(np.linalg.norm(best[0][:3] - wl.truth[:3]))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": load_traffic() if args.workload == "c1" else None,
+                     "kernel": "k_swarm_iter", "avg_launch_ms": avg_launch_s * 1e3,
+                     "flop_per_launch": flop_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, obs, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

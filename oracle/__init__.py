@@ -64,6 +64,7 @@ def _load():
     if not os.path.exists(_LIB):
         build()
     lib = C.CDLL(_LIB)
+    lib.orc_num_threads.restype = C.c_int
     lib.orc_rhs.argtypes = [C.c_double, _D, _D]
     lib.orc_rk4_step.argtypes = [C.c_double, C.c_double, _D]
     lib.orc_schedule.argtypes = [_D, C.c_int32, C.c_double, _I64, _D]
@@ -125,6 +126,11 @@ class Pso:
         self.lo, self.hi = _f64(lo).ravel(), _f64(hi).ravel()
         self._s = _Pso(self.omega, self.eta1, self.eta2, self.seed, self.problem,
                        (C.c_double * 6)(*self.lo), (C.c_double * 6)(*self.hi))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().orc_num_threads()
 
 
 def rhs(mu, s):

@@ -38,6 +38,7 @@
  * from numpy).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -339,6 +340,12 @@ static double cost_one(const orc_problem *P, const tables *T, const double x0[6]
             J = fma(e, e, J);
     }
     return J;
+}
+
+/* Threads the parallel loops below use. */
+int orc_num_threads(void)
+{
+    return omp_get_max_threads();
 }
 
 /* Costs of m particles; x is [m][6]. */

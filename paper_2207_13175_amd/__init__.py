@@ -1,0 +1,265 @@
+"""Particle-swarm initial orbit determination in the CR3BP on MI355X.
+
+Thin Python binding of ``libiod.so`` (C ABI in ``include/iod.h``), after
+Zuehlke et al., "Initial Orbit Determination for the CR3BP using Particle
+Swarm Optimization" (AAS 22-770, arXiv 2207.13175). Functions carry the C
+names; they only marshal arguments. Device memory and streams come from
+PyTorch (HIP build): swarm arrays are float64 tensors on the GPU laid out
+structure-of-arrays, ``[6, ld]`` for states and ``[ld]`` for costs. Every
+step of the computation runs in the library's HIP kernels; there is no
+other code path, and calls fail if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiod.so")
+
+IOD_OK = 0
+IOD_EINVAL = -1
+IOD_EDEVICE = -2
+IOD_ENOMEM = -3
+IOD_ESTATE = -4
+IOD_COST_PAPER = 0
+IOD_COST_CHI2 = 1
+IOD_MAX_OBS = 65536
+
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+
+
+class IodError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libiod error {code}: {msg}")
+        self.code = code
+
+
+class iod_options(C.Structure):
+    _fields_ = [("h", C.c_double), ("cost_mode", C.c_int32), ("reserved", C.c_int32)]
+
+
+class iod_pso_params(C.Structure):
+    _fields_ = [("omega", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double),
+                ("seed", C.c_uint64), ("problem", C.c_uint64),
+                ("lo", C.c_double * 6), ("hi", C.c_double * 6)]
+
+
+class iod_swarm(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("v", C.c_void_p), ("p", C.c_void_p),
+                ("jp", C.c_void_p), ("cost", C.c_void_p), ("work", C.c_void_p),
+                ("hist", C.c_void_p), ("hist_len", C.c_int64), ("ld", C.c_int64),
+                ("m", C.c_int64), ("iter", C.c_int64)]
+
+
+# name -> (restype, argtypes); the exported C ABI
+_SIGNATURES = {
+    "iod_version": (C.c_int, []),
+    "iod_last_error": (C.c_char_p, []),
+    "iod_schedule": (C.c_int, [_D, C.c_int32, C.c_double, _I64, _D]),
+    "iod_create": (C.c_int, [C.c_double, _D, _D, _D, C.c_int32, C.c_double,
+                             C.POINTER(iod_options), C.POINTER(C.c_void_p)]),
+    "iod_destroy": (C.c_int, [C.c_void_p]),
+    "iod_num_obs": (C.c_int32, [C.c_void_p]),
+    "iod_chief_positions": (C.c_int, [C.c_void_p, _D]),
+    "iod_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "iod_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "iod_eval_swarm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "iod_swarm_work_len": (C.c_int64, [C.c_int64]),
+    "iod_swarm_init": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), C.POINTER(iod_pso_params), C.c_void_p]),
+    "iod_step": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), C.POINTER(iod_pso_params), C.c_int64, C.c_void_p]),
+    "iod_swarm_best": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), _D, _D, _I64, C.c_void_p]),
+    "iod_solve": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), C.c_int64, C.c_int64, _D, _D, _D]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libiod (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise IodError(rc, iod_last_error())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, shape=None):
+    """Device pointer of a contiguous float64 GPU tensor (shape-checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a torch tensor on a GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def iod_version() -> int:
+    return lib().iod_version()
+
+
+def iod_last_error() -> str:
+    return lib().iod_last_error().decode()
+
+
+def iod_schedule(obs_times, h):
+    t = np.ascontiguousarray(obs_times, dtype=np.float64).ravel()
+    ns = np.empty(len(t), dtype=np.int64)
+    tau = np.empty(len(t))
+    _check(lib().iod_schedule(_dp(t), len(t), float(h), ns.ctypes.data_as(_I64), _dp(tau)))
+    return ns, tau
+
+
+class Handle:
+    """Owns an iod_handle; destroyed with the object (or by iod_destroy)."""
+
+    def __init__(self, ptr, K):
+        self.ptr = ptr
+        self.K = K
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.iod_destroy(self.ptr)
+            self.ptr = None
+
+
+def iod_create(mu, chief_state, obs_times, obs_angles, sigma, h=1e-3, cost_mode=IOD_COST_PAPER):
+    chief = np.ascontiguousarray(chief_state, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(obs_times, dtype=np.float64).ravel()
+    ang = np.ascontiguousarray(obs_angles, dtype=np.float64).reshape(-1)
+    if chief.size != 6 or ang.size != 2 * t.size:
+        raise ValueError("chief_state must have 6 values and obs_angles [K, 2]")
+    opt = iod_options(float(h), int(cost_mode), 0)
+    out = C.c_void_p()
+    _check(lib().iod_create(float(mu), _dp(chief), _dp(t), _dp(ang), len(t), float(sigma),
+                            C.byref(opt), C.byref(out)))
+    return Handle(out, len(t))
+
+
+def iod_destroy(handle: Handle):
+    if handle.ptr:
+        rc = lib().iod_destroy(handle.ptr)
+        handle.ptr = None
+        _check(rc)
+
+
+def iod_chief_positions(handle: Handle):
+    out = np.empty((handle.K, 3))
+    _check(lib().iod_chief_positions(handle.ptr, _dp(out)))
+    return out
+
+
+def iod_propagate(handle: Handle, x, m, states, stream=None):
+    """x: [6, ld] -> states: [K, 6, ld]."""
+    ld = x.shape[1]
+    _check(lib().iod_propagate(handle.ptr, _dev(x, (6, ld)), ld, int(m),
+                               _dev(states, (handle.K, 6, ld)), _stream(stream)))
+
+
+def iod_predict(handle: Handle, x, m, angles, stream=None):
+    """x: [6, ld] -> angles: [K, 2, ld] (azimuth, elevation)."""
+    ld = x.shape[1]
+    _check(lib().iod_predict(handle.ptr, _dev(x, (6, ld)), ld, int(m),
+                             _dev(angles, (handle.K, 2, ld)), _stream(stream)))
+
+
+def iod_eval_swarm(handle: Handle, x, m, cost, stream=None):
+    """x: [6, ld] -> cost: [ld] (first m written)."""
+    ld = x.shape[1]
+    _check(lib().iod_eval_swarm(handle.ptr, _dev(x, (6, ld)), ld, int(m), _dev(cost, (ld,)),
+                                _stream(stream)))
+
+
+def iod_swarm_work_len(m) -> int:
+    return _check(lib().iod_swarm_work_len(int(m)))
+
+
+def pso_params(omega, eta1, eta2, seed, lo, hi, problem=0) -> iod_pso_params:
+    lo = np.asarray(lo, dtype=np.float64).ravel()
+    hi = np.asarray(hi, dtype=np.float64).ravel()
+    return iod_pso_params(float(omega), float(eta1), float(eta2), int(seed), int(problem),
+                          (C.c_double * 6)(*lo), (C.c_double * 6)(*hi))
+
+
+class Swarm:
+    """Device swarm arrays (torch float64) plus the iod_swarm view of them."""
+
+    def __init__(self, m, device="cuda", ld=None, hist_len=0):
+        import torch
+        self.m = int(m)
+        self.ld = int(ld) if ld is not None else (self.m + 63) // 64 * 64
+        kw = dict(dtype=torch.float64, device=device)
+        self.x = torch.zeros((6, self.ld), **kw)
+        self.v = torch.zeros((6, self.ld), **kw)
+        self.p = torch.zeros((6, self.ld), **kw)
+        self.jp = torch.zeros(self.ld, **kw)
+        self.cost = torch.zeros(self.ld, **kw)
+        self.work = torch.zeros(iod_swarm_work_len(self.m), **kw)
+        self.hist = torch.zeros(max(hist_len, 1), **kw)
+        self.s = iod_swarm(self.x.data_ptr(), self.v.data_ptr(), self.p.data_ptr(),
+                           self.jp.data_ptr(), self.cost.data_ptr(), self.work.data_ptr(),
+                           self.hist.data_ptr() if hist_len > 0 else None, int(hist_len),
+                           self.ld, self.m, -1)
+
+    @property
+    def iter(self):
+        return self.s.iter
+
+
+def iod_swarm_init(handle: Handle, swarm: Swarm, params: iod_pso_params, stream=None):
+    _check(lib().iod_swarm_init(handle.ptr, C.byref(swarm.s), C.byref(params), _stream(stream)))
+
+
+def iod_step(handle: Handle, swarm: Swarm, params: iod_pso_params, n_iter, stream=None):
+    _check(lib().iod_step(handle.ptr, C.byref(swarm.s), C.byref(params), int(n_iter),
+                          _stream(stream)))
+
+
+def iod_swarm_best(handle: Handle, swarm: Swarm, stream=None):
+    """(best state [6], best cost, best index); synchronises the stream."""
+    st = np.empty(6)
+    J = C.c_double()
+    idx = C.c_int64()
+    _check(lib().iod_swarm_best(handle.ptr, C.byref(swarm.s), _dp(st), C.byref(J), C.byref(idx),
+                                _stream(stream)))
+    return st, J.value, idx.value
+
+
+def iod_solve(handle: Handle, params: iod_pso_params, m, n_iter):
+    """(best state [6], best cost, history [n_iter + 1]); synchronous."""
+    st = np.empty(6)
+    J = C.c_double()
+    hist = np.empty(int(n_iter) + 1)
+    _check(lib().iod_solve(handle.ptr, C.byref(params), int(m), int(n_iter), _dp(st), C.byref(J),
+                           _dp(hist)))
+    return st, J.value, hist

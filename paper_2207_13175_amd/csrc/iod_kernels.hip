@@ -1,0 +1,548 @@
+// iod_kernels.hip -- gfx950 kernels of libiod: CR3BP RK4 propagation, the
+// azimuth/elevation residual cost and the particle-swarm update with its
+// global-best reduction (Zuehlke et al., AAS 22-770: eqs. cr3bp:x-z,
+// rel:pos, meas:function, b:total, total:cost; Algorithm 1).
+//
+// Design (CDNA4, wave64):
+//   - One particle per lane. Its state, the RK4 stage input, the running
+//     stage sum and the current derivative live in VGPRs for the whole
+//     propagation; nothing touches memory inside the step loop.
+//   - The observation table (step counts, chief positions, sin/cos of the
+//     observed angles) is staged in LDS by each workgroup and read as a
+//     broadcast; step counts are made wave-uniform with readfirstlane so the
+//     step loop is scalar control flow.
+//   - Swarm arrays are structure-of-arrays FP64 ([6][ld]), so every load and
+//     store of a component is one coalesced 512-byte wave access.
+//   - The per-iteration global best is reduced without atomics: each
+//     workgroup writes its argmin (cost, index, position) to a slot; the next
+//     launch has every workgroup reduce all slots with the same deterministic
+//     lexicographic (cost, index) order, and workgroup 0 records the result.
+//     Slots and records are double-buffered by iteration parity.
+//   - Random numbers are counter-based Philox4x64-10, so every (iteration,
+//     particle) draw is independent of launch shape and replayable.
+//
+// Arithmetic: FP64, compiled with -ffp-contract=off; every fused
+// multiply-add is explicit. The evaluation order of the right-hand side, the
+// RK4 combination, the residual and the swarm update is one fixed order
+// (written out in each function) so that a CPU implementation following the
+// same order produces the same bits; sqrt and division are the correctly
+// rounded device operations. MFMA is not used: nothing here is a dense
+// contraction; the bound is the FP64 vector ALU.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "iod_internal.h"
+
+namespace iodk {
+
+// ---------------------------------------------------------------------------
+// Dynamics: eqs. cr3bp:x-z in the rotating barycentric frame.
+// ---------------------------------------------------------------------------
+
+// f(s) for s = (x, y, z, vx, vy, vz):
+//   ax =  2 vy + x - (1-mu)(x+mu)/r1^3 - mu (x-(1-mu))/r2^3
+//   ay = -2 vx + y - ((1-mu)/r1^3 + mu/r2^3) y
+//   az =           - ((1-mu)/r1^3 + mu/r2^3) z
+__device__ __forceinline__ void rhs(double mu, double mu1, const double s[6], double f[6])
+{
+    const double x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4];
+    const double d1 = x + mu;
+    const double d2 = x - mu1;
+    const double q = fma(z, z, y * y);
+    const double r1s = fma(d1, d1, q);
+    const double r2s = fma(d2, d2, q);
+    const double c1 = mu1 / (r1s * sqrt(r1s));
+    const double c2 = mu / (r2s * sqrt(r2s));
+    const double cs = c1 + c2;
+    f[0] = s[3];
+    f[1] = s[4];
+    f[2] = s[5];
+    f[3] = fma(-c2, d2, fma(-c1, d1, fma(2.0, vy, x)));
+    f[4] = fma(-cs, y, fma(-2.0, vx, y));
+    f[5] = -(cs * z);
+}
+
+// Classical RK4 step of size h (h2 = h/2, h6 = h/6), in place. The stage sum
+// a = k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are produced, so
+// only X, a, the stage input and one derivative are live.
+__device__ __forceinline__ void rk4(double mu, double mu1, double h, double h2, double h6,
+                                    double X[6])
+{
+    double k[6], a[6], s[6];
+    rhs(mu, mu1, X, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = k[d];
+        s[d] = fma(h2, k[d], X[d]);
+    }
+    rhs(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s[d] = fma(h2, k[d], X[d]);
+    }
+    rhs(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s[d] = fma(h, k[d], X[d]);
+    }
+    rhs(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = a[d] + k[d];
+        X[d] = fma(h6, a[d], X[d]);
+    }
+}
+
+// Walk the observation schedule: advance X on the grid, and at each
+// observation hand the state there (a side copy advanced by the partial step
+// when the time is off the grid) to `obs(row, S)`. Every thread of the
+// workgroup must call this (it stages the table through LDS with barriers).
+template <class Obs>
+__device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, Obs &obs)
+{
+    int32_t step = 0;
+    for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
+        const int32_t nk = min(OBS_CHUNK, A.K - k0);
+        __syncthreads();
+        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
+            lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
+        __syncthreads();
+        for (int32_t kk = 0; kk < nk; ++kk) {
+            const double *row = lds + kk * TAB_W;
+            const int32_t target = __builtin_amdgcn_readfirstlane((int32_t)row[TAB_NS]);
+            for (; step < target; ++step) rk4(A.mu, A.mu1, A.h, A.h2, A.h6, X);
+            const double tau = row[TAB_TAU];
+            double S[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) S[d] = X[d];
+            if (tau != 0.0) rk4(A.mu, A.mu1, tau, 0.5 * tau, tau / 6.0, S);
+            obs(row, S);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Measurement model and cost: eqs. rel:pos, meas:function, b:total,
+// total:cost.
+// ---------------------------------------------------------------------------
+
+// Residual-squared accumulator. rho = r - r_chief; the azimuth and elevation
+// residuals (observed - predicted, azimuth wrapped to (-pi, pi]) come from
+// the angle-difference identities
+//   |rho_xy| sin(da) = sa rho_x - ca rho_y,  |rho_xy| cos(da) = ca rho_x + sa rho_y
+//   |rho|    sin(db) = sb rho_xy - cb rho_z, |rho|    cos(db) = cb rho_xy + sb rho_z
+// so atan2 acts on the residual itself. rho_xy = 0 means the predicted
+// azimuth is atan2(0, 0) = 0; rho = 0 has no line of sight and e = +inf.
+// e_k = w (da^2 + db^2); J = sum e_k^2 (mode 0) or sum e_k (mode 1).
+struct CostAcc {
+    double J, w;
+    int32_t mode;
+    __device__ __forceinline__ void operator()(const double *row, const double S[6])
+    {
+        const double rx = S[0] - row[TAB_RC + 0];
+        const double ry = S[1] - row[TAB_RC + 1];
+        const double rz = S[2] - row[TAB_RC + 2];
+        const double sa = row[TAB_SA], ca = row[TAB_CA], sb = row[TAB_SB], cb = row[TAB_CB];
+        double e;
+        if (rx == 0.0 && ry == 0.0 && rz == 0.0) {
+            e = INFINITY;
+        } else {
+            const double rxy = sqrt(fma(rx, rx, ry * ry));
+            double na, nd;
+            if (rxy == 0.0) {
+                na = sa;
+                nd = ca;
+            } else {
+                na = fma(sa, rx, -(ca * ry));
+                nd = fma(ca, rx, sa * ry);
+            }
+            const double da = atan2(na, nd);
+            const double db = atan2(fma(sb, rxy, -(cb * rz)), fma(cb, rxy, sb * rz));
+            e = w * fma(da, da, db * db);
+        }
+        J = (mode == 1) ? J + e : fma(e, e, J);
+    }
+};
+
+__device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], double *lds)
+{
+    double X[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = x0[d];
+    CostAcc acc{0.0, A.w, A.mode};
+    walk(A, X, lds, acc);
+    return acc.J;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B97F4A7C15ULL;
+            k1 += 0xBB67AE8584CAA73BULL;
+        }
+        const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ULL, c[0]);
+        const uint64_t lo0 = 0xD2E7470EE14C6C93ULL * c[0];
+        const uint64_t hi1 = __umul64hi(0xCA5A826395121157ULL, c[2]);
+        const uint64_t lo1 = 0xCA5A826395121157ULL * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ double u01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+// ---------------------------------------------------------------------------
+// Argmin reductions: lexicographic (key, index), NaN ranked as +inf.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double cost_key(double J) { return isnan(J) ? INFINITY : J; }
+
+__device__ __forceinline__ bool lex_less(double ka, double ia, double kb, double ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+// Block-wide argmin; every thread returns the minimum. red: LDS [2 * BS/64].
+__device__ __forceinline__ void block_argmin(double &key, double &idx, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ok = __shfl_xor(key, off, 64);
+        const double oi = __shfl_xor(idx, off, 64);
+        if (lex_less(ok, oi, key, idx)) {
+            key = ok;
+            idx = oi;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * wave] = key;
+        red[2 * wave + 1] = idx;
+    }
+    __syncthreads();
+    key = red[0];
+    idx = red[1];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (lex_less(red[2 * w], red[2 * w + 1], key, idx)) {
+            key = red[2 * w];
+            idx = red[2 * w + 1];
+        }
+    __syncthreads();
+}
+
+// Workgroup argmin of (key(jp), i) over its valid particles, written with the
+// winner's state to slot `slot` as [key, index, state[6]].
+__device__ __forceinline__ void write_slot(double jp, int64_t i, bool valid, const double st[6],
+                                           double *slot, double *red, double *wst)
+{
+    double key = valid ? cost_key(jp) : INFINITY;
+    double idx = valid ? (double)i : INFINITY;
+    block_argmin(key, idx, red);
+    if (valid && (double)i == idx) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) wst[d] = st[d];
+    }
+    __syncthreads();
+    if (threadIdx.x < REC) slot[threadIdx.x] = threadIdx.x == 0 ? key : threadIdx.x == 1 ? idx : wst[threadIdx.x - 2];
+}
+
+// Global best G_{n-1} = merge(record G_{n-2}, slots of launch n-1): the slot
+// minimum replaces the record if the record is empty (index < 0) or the slot
+// cost is strictly lower. Every workgroup computes the same result.
+__device__ __forceinline__ void reduce_global(const double *slots, int64_t nslots,
+                                              const double *prev, double g[6], double &gkey,
+                                              double &gidx, double *red)
+{
+    double key = INFINITY, idx = INFINITY;
+    for (int64_t s = threadIdx.x; s < nslots; s += blockDim.x) {
+        const double k = slots[s * REC], i = slots[s * REC + 1];
+        if (lex_less(k, i, key, idx)) {
+            key = k;
+            idx = i;
+        }
+    }
+    block_argmin(key, idx, red);
+    const double pk = prev[0], pi = prev[1];
+    if (pi < 0.0 || key < pk) {
+        const int64_t s = (int64_t)idx / BS;
+        gkey = key;
+        gidx = idx;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = slots[s * REC + 2 + d];
+    } else {
+        gkey = pk;
+        gidx = pi;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = prev[2 + d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+struct StoreStates {
+    double *out;
+    int64_t ld, i;
+    int32_t k;
+    bool valid;
+    __device__ __forceinline__ void operator()(const double *, const double S[6])
+    {
+        if (valid) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) out[((int64_t)k * 6 + d) * ld + i] = S[d];
+        }
+        ++k;
+    }
+};
+
+struct StoreAngles {
+    double *out;
+    int64_t ld, i;
+    int32_t k;
+    bool valid;
+    __device__ __forceinline__ void operator()(const double *row, const double S[6])
+    {
+        // L = rho / |rho|, azimuth = atan2(L_y, L_x), elevation = asin(L_z)
+        const double rx = S[0] - row[TAB_RC + 0];
+        const double ry = S[1] - row[TAB_RC + 1];
+        const double rz = S[2] - row[TAB_RC + 2];
+        const double r = sqrt(rx * rx + ry * ry + rz * rz);
+        double az = NAN, el = NAN;
+        if (r != 0.0) {
+            az = atan2(ry / r, rx / r);
+            el = asin(rz / r);
+        }
+        if (valid) {
+            out[((int64_t)k * 2 + 0) * ld + i] = az;
+            out[((int64_t)k * 2 + 1) * ld + i] = el;
+        }
+        ++k;
+    }
+};
+
+__device__ __forceinline__ void load_state(const double *x, int64_t ld, int64_t j, double X[6])
+{
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = x[d * ld + j];
+}
+
+__global__ __launch_bounds__(BS) void k_propagate(KArgs A, const double *__restrict__ x,
+                                                  int64_t ld, int64_t m,
+                                                  double *__restrict__ states)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = i < m;
+    double X[6];
+    load_state(x, ld, valid ? i : m - 1, X);
+    StoreStates obs{states, ld, i, 0, valid};
+    walk(A, X, lds, obs);
+}
+
+__global__ __launch_bounds__(BS) void k_predict(KArgs A, const double *__restrict__ x,
+                                                int64_t ld, int64_t m,
+                                                double *__restrict__ angles)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = i < m;
+    double X[6];
+    load_state(x, ld, valid ? i : m - 1, X);
+    StoreAngles obs{angles, ld, i, 0, valid};
+    walk(A, X, lds, obs);
+}
+
+__global__ __launch_bounds__(BS) void k_eval(KArgs A, const double *__restrict__ x, int64_t ld,
+                                             int64_t m, double *__restrict__ cost)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = i < m;
+    double X[6];
+    load_state(x, ld, valid ? i : m - 1, X);
+    const double J = eval_cost(A, X, lds);
+    if (valid) cost[i] = J;
+}
+
+// Algorithm 1 initialisation.
+__global__ __launch_bounds__(BS) void k_swarm_init(KArgs A, PsoArgs P, SwarmArgs S)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ double red[2 * (BS / 64)];
+    __shared__ double wst[6];
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = i < S.m;
+    const int64_t j = valid ? i : S.m - 1;
+    uint64_t u[8] = {0, (uint64_t)j, P.problem, 0, 1, (uint64_t)j, P.problem, 0};
+    philox4x64_10(u, P.seed, 0);
+    philox4x64_10(u + 4, P.seed, 0);
+    double X[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = P.lo[d] + (P.hi[d] - P.lo[d]) * u01(u[d]);
+    const double J = eval_cost(A, X, lds);
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            S.x[d * S.ld + i] = X[d];
+            S.v[d * S.ld + i] = 0.0;
+            S.p[d * S.ld + i] = X[d];
+        }
+        S.jp[i] = J;
+        S.cost[i] = J;
+    }
+    double *slots0 = S.work;  // parity 0
+    write_slot(J, i, valid, X, slots0 + (int64_t)blockIdx.x * REC, red, wst);
+    if (blockIdx.x == 0 && threadIdx.x < REC) {
+        // record parity 1 = "before initialisation": empty
+        double *rec1 = S.work + 2 * S.nslots * REC + REC;
+        rec1[threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
+    }
+}
+
+// Algorithm 1, iteration n >= 1.
+__global__ __launch_bounds__(BS) void k_swarm_iter(KArgs A, PsoArgs P, SwarmArgs S, int64_t n)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ double red[2 * (BS / 64)];
+    __shared__ double wst[6];
+    double *slots = S.work;
+    double *recs = S.work + 2 * S.nslots * REC;
+    const double *slots_prev = slots + ((n - 1) & 1) * S.nslots * REC;
+    double *slots_cur = slots + (n & 1) * S.nslots * REC;
+
+    // (a) global best of the previous iteration
+    double g[6], gkey, gidx;
+    reduce_global(slots_prev, S.nslots, recs + (n & 1) * REC, g, gkey, gidx, red);
+    if (blockIdx.x == 0) {
+        double *rec = recs + ((n - 1) & 1) * REC;
+        if (threadIdx.x < REC)
+            rec[threadIdx.x] = threadIdx.x == 0 ? gkey : threadIdx.x == 1 ? gidx : g[threadIdx.x - 2];
+        if (threadIdx.x == 0 && S.hist && n - 1 < S.hist_len) S.hist[n - 1] = gkey;
+    }
+
+    // (b) evaluate, personal best, velocity and position
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool valid = i < S.m;
+    const int64_t j = valid ? i : S.m - 1;
+    const int64_t ld = S.ld;
+    double X[6], V[6], Pb[6];
+    load_state(S.x, ld, j, X);
+    load_state(S.v, ld, j, V);
+    load_state(S.p, ld, j, Pb);
+    double jp = S.jp[j];
+    double J;
+    if (n >= 2)
+        J = eval_cost(A, X, lds);
+    else
+        J = S.cost[j];
+    const bool better = cost_key(J) < cost_key(jp);
+    if (better) {
+        jp = J;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Pb[d] = X[d];
+    }
+    uint64_t c[4] = {(uint64_t)n, (uint64_t)j, P.problem, 1};
+    philox4x64_10(c, P.seed, 0);
+    const double a1 = P.eta1 * u01(c[0]);
+    const double a2 = P.eta2 * u01(c[1]);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const double vn = P.omega * V[d] + a1 * (Pb[d] - X[d]) + a2 * (g[d] - X[d]);
+        V[d] = vn;
+        X[d] = X[d] + vn;
+    }
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            S.x[d * ld + i] = X[d];
+            S.v[d * ld + i] = V[d];
+        }
+        if (n >= 2) S.cost[i] = J;
+        if (better) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) S.p[d * ld + i] = Pb[d];
+            S.jp[i] = jp;
+        }
+    }
+
+    // (c) this workgroup's best personal best, for the next launch
+    write_slot(jp, i, valid, Pb, slots_cur + (int64_t)blockIdx.x * REC, red, wst);
+}
+
+// Global best after iteration n: G_n = merge(G_{n-1}, slots of launch n).
+__global__ __launch_bounds__(BS) void k_swarm_final(SwarmArgs S, int64_t n)
+{
+    __shared__ double red[2 * (BS / 64)];
+    double *slots = S.work;
+    double *recs = S.work + 2 * S.nslots * REC;
+    double g[6], gkey, gidx;
+    reduce_global(slots + (n & 1) * S.nslots * REC, S.nslots, recs + ((n - 1) & 1) * REC, g,
+                  gkey, gidx, red);
+    double *rec = recs + (n & 1) * REC;
+    if (threadIdx.x < REC)
+        rec[threadIdx.x] = threadIdx.x == 0 ? gkey : threadIdx.x == 1 ? gidx : g[threadIdx.x - 2];
+    if (threadIdx.x == 0 && S.hist && n < S.hist_len) S.hist[n] = gkey;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+
+static inline unsigned grid_for(int64_t m) { return (unsigned)((m + BS - 1) / BS); }
+
+hipError_t launch_propagate(const KArgs &A, const double *x, int64_t ld, int64_t m,
+                            double *states, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_propagate, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, states);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m,
+                          double *angles, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_predict, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, angles);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const KArgs &A, const double *x, int64_t ld, int64_t m, double *cost,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_eval, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, cost);
+    return hipGetLastError();
+}
+
+hipError_t launch_swarm_init(const KArgs &A, const PsoArgs &P, const SwarmArgs &S,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_swarm_init, dim3(grid_for(S.m)), dim3(BS), 0, st, A, P, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_swarm_iter(const KArgs &A, const PsoArgs &P, const SwarmArgs &S, int64_t n,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_swarm_iter, dim3(grid_for(S.m)), dim3(BS), 0, st, A, P, S, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_swarm_final(const SwarmArgs &S, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_swarm_final, dim3(1), dim3(BS), 0, st, S, n);
+    return hipGetLastError();
+}
+
+}  // namespace iodk

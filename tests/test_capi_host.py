@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/iod.h, computes the observation schedule
+like the oracle, and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2207_13175_amd as iod
+from paper_2207_13175_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "iod.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(iod_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = C.CDLL(iod.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding wraps every exported function
+    assert set(names) <= set(iod._SIGNATURES)
+
+
+def test_version_and_error():
+    assert iod.iod_version() >= 10000
+    assert isinstance(iod.iod_last_error(), str)
+
+
+@pytest.mark.parametrize("t,h", [
+    (W.even_times(0.5, 10), 1e-3),
+    (W.even_times(2.0, 40), 5e-4),
+    ([0.0, 0.0123, 0.02, 0.5 + 3e-10, 0.7], 1e-3),
+    (np.cumsum(np.random.default_rng(0).uniform(1e-4, 0.1, 80)), 1e-3),
+])
+def test_schedule_matches_oracle(orc, t, h):
+    ns, tau = iod.iod_schedule(t, h)
+    ns_o, tau_o = orc.schedule(t, h)
+    assert np.array_equal(ns, ns_o) and np.array_equal(tau, tau_o)
+
+
+@pytest.mark.parametrize("t,h", [([0.1, 0.1], 1e-3), ([0.2, 0.1], 1e-3), ([-1e-3], 1e-3),
+                                 ([np.nan], 1e-3), ([0.1], 0.0), ([0.1], -1e-3),
+                                 ([0.1], np.inf), ([1e9], 1e-3)])
+def test_schedule_rejects(t, h):
+    with pytest.raises(iod.IodError) as e:
+        iod.iod_schedule(t, h)
+    assert e.value.code == iod.IOD_EINVAL
+
+
+def _create_raw(mu=0.0121, chief=None, t=None, ang=None, K=None, sigma=1e-5, opt=None, out=True):
+    L = iod.lib()
+    chief = np.array(W.C0_CHIEF if chief is None else chief, dtype=np.float64)
+    t = np.array(W.even_times(0.5, 10) if t is None else t, dtype=np.float64)
+    ang = np.zeros((len(t), 2)) if ang is None else np.array(ang, dtype=np.float64)
+    K = len(t) if K is None else K
+    h = C.c_void_p()
+    return L.iod_create(mu, iod._dp(chief), iod._dp(t), iod._dp(ang), K, sigma,
+                        C.byref(opt) if opt is not None else None, C.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(mu=-0.1), dict(mu=0.6), dict(mu=float("nan")),
+    dict(chief=[1, 0, np.inf, 0, 0, 0]),
+    dict(sigma=0.0), dict(sigma=-1.0), dict(sigma=float("inf")),
+    dict(K=0), dict(K=-3),
+    dict(t=[0.1, 0.05]), dict(t=[-0.1, 0.2]),
+    dict(ang=[[0.0, np.nan]] * 10),
+    dict(opt=iod.iod_options(0.0, 0, 0)), dict(opt=iod.iod_options(1e-3, 7, 0)),
+    dict(opt=iod.iod_options(1e-3, 0, 1)),
+    dict(out=False),
+])
+def test_create_rejects_invalid(kw):
+    rc = _create_raw(**kw)
+    assert rc == iod.IOD_EINVAL, (kw, rc, iod.iod_last_error())
+    assert iod.iod_last_error() != ""
+
+
+def test_calls_reject_null_handle_and_bad_shapes():
+    L = iod.lib()
+    dummy = C.c_void_p(16)
+    assert L.iod_eval_swarm(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
+    assert L.iod_propagate(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
+    assert L.iod_predict(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
+    assert L.iod_destroy(None) == iod.IOD_OK
+    assert L.iod_num_obs(None) == iod.IOD_EINVAL
+    assert L.iod_swarm_work_len(0) == iod.IOD_EINVAL
+    assert L.iod_swarm_work_len(1) > 0
+    assert L.iod_swarm_work_len(65536) == 2 * 256 * 8 + 16
+    p = iod.pso_params(0.7, 1.5, 1.5, 0, np.zeros(6), np.ones(6))
+    assert L.iod_solve(None, C.byref(p), 10, 10, None, None, None) == iod.IOD_EINVAL
+    assert L.iod_step(None, None, C.byref(p), 1, None) == iod.IOD_EINVAL

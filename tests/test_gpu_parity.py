@@ -1,0 +1,315 @@
+"""GPU parity: libiod (through its C ABI) against the FP64 CPU oracle.
+
+Bars: propagated states and chief positions bit-exact; per-particle FP64 cost
+within 1e-11 relative; swarm states, personal bests and the global-best
+index bit-exact after initialisation and iterations; predicted angles within a
+few ulp (the two sides call different atan2/asin implementations).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2207_13175_amd as iod
+from paper_2207_13175_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COST_RTOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def make_problem(wl, noise=True, mode=0):
+    P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((wl.K, 2)), mode)
+    obs = oracle.predict(P0, wl.truth) + (wl.noise if noise else 0.0)
+    return P0.with_angles(obs), obs
+
+
+def to_dev(torch, dev, xs, ld=None):
+    m = len(xs)
+    ld = ld or (m + 63) // 64 * 64
+    x = torch.zeros((6, ld), dtype=torch.float64, device=dev)
+    x[:, :m] = torch.from_numpy(np.ascontiguousarray(xs.T)).to(dev)
+    return x
+
+
+def gpu_cost(torch, dev, h, xs, ld=None):
+    x = to_dev(torch, dev, xs, ld)
+    cost = torch.full((x.shape[1],), -7.0, dtype=torch.float64, device=dev)
+    iod.iod_eval_swarm(h, x, len(xs), cost)
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    assert np.all(c[len(xs):] == -7.0), "wrote past m"
+    return c[:len(xs)]
+
+
+def assert_cost_parity(got, want):
+    fin = np.isfinite(want)
+    assert np.array_equal(np.isfinite(got), fin)
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.array_equal(got[~fin & ~np.isnan(want)], want[~fin & ~np.isnan(want)])
+    rel = np.abs(got[fin] - want[fin]) / np.maximum(np.abs(want[fin]), 1e-300)
+    assert rel.size == 0 or rel.max() <= COST_RTOL, f"max rel err {rel.max():.3e}"
+    return rel.max() if rel.size else 0.0
+
+
+def test_chief_positions_bitwise(torch_dev):
+    for wl in (W.c0(0), W.c1(0, m=64, n_iter=1)):
+        P, obs = make_problem(wl)
+        h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+        want = oracle.propagate(wl.mu, wl.h, wl.chief, wl.t)[:, :3]
+        assert np.array_equal(iod.iod_chief_positions(h), want)
+
+
+@pytest.mark.parametrize("m,ld", [(300, 320), (1, 64), (64, 64), (65, 192)])
+def test_propagate_bitwise_ragged_and_off_grid(torch_dev, m, ld):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    t = np.array([0.0, 0.0123, 0.05, 0.1007, 0.25])   # on- and off-grid, one at the epoch
+    h = iod.iod_create(wl.mu, wl.chief, t, np.zeros((len(t), 2)), wl.sigma, h=wl.h)
+    xs = W.random_swarm(2, m, wl.lo, wl.hi)
+    x = to_dev(torch, dev, xs, ld)
+    st = torch.full((len(t), 6, ld), -7.0, dtype=torch.float64, device=dev)
+    iod.iod_propagate(h, x, m, st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    assert np.all(got[:, :, m:] == -7.0)
+    for i in range(m):
+        want = oracle.propagate(wl.mu, wl.h, xs[i], t)
+        assert np.array_equal(got[:, :, i], want), i
+
+
+def test_propagate_bitwise_c1_shape(torch_dev):
+    torch, dev = torch_dev
+    wl = W.c1(0, m=256, n_iter=1)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, np.zeros((wl.K, 2)), wl.sigma, h=wl.h)
+    xs = W.random_swarm(3, 256, wl.lo, wl.hi)
+    x = to_dev(torch, dev, xs)
+    st = torch.zeros((wl.K, 6, 256), dtype=torch.float64, device=dev)
+    iod.iod_propagate(h, x, 256, st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    for i in range(0, 256, 37):
+        assert np.array_equal(got[:, :, i], oracle.propagate(wl.mu, wl.h, xs[i], wl.t)), i
+
+
+def test_predict_angles(torch_dev):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    xs = np.vstack([wl.truth, W.random_swarm(4, 99, wl.lo, wl.hi), wl.chief])
+    m = len(xs)
+    x = to_dev(torch, dev, xs)
+    ang = torch.zeros((wl.K, 2, x.shape[1]), dtype=torch.float64, device=dev)
+    iod.iod_predict(h, x, m, ang)
+    torch.cuda.synchronize()
+    got = ang.cpu().numpy()
+    for i in range(m - 1):
+        want = oracle.predict(P, xs[i])
+        assert np.max(np.abs(got[:, :, i] - want)) <= 4e-15, i
+    # the chief itself: no line of sight
+    assert np.all(np.isnan(got[:, :, m - 1]))
+    # noise-free observations reproduce the truth's prediction
+    assert np.max(np.abs(got[:, :, 0] - (obs - wl.noise))) <= 4e-15
+
+
+@pytest.mark.parametrize("mode", [iod.IOD_COST_PAPER, iod.IOD_COST_CHI2])
+@pytest.mark.parametrize("m,ld", [(256, 256), (300, 320), (1, 64), (65, 128)])
+def test_eval_parity_c0(torch_dev, mode, m, ld):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl, mode=mode)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h, cost_mode=mode)
+    xs = W.random_swarm(5, m, wl.lo, wl.hi)
+    if m >= 4:
+        # near-truth particles: the smallest residuals, the hardest relative bar
+        xs[0] = wl.truth
+        xs[1] = wl.truth + 1e-9
+        xs[2] = wl.truth - np.array([1e-7, 0, 0, 0, 1e-7, 0])
+    rel = assert_cost_parity(gpu_cost(torch, dev, h, xs, ld), oracle.cost(P, xs))
+    print(f"m={m} ld={ld} mode={mode} max rel err {rel:.2e}")
+
+
+def test_eval_nonfinite_cases(torch_dev):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    xs = np.vstack([
+        wl.chief,                                          # on the chief: rho = 0 -> +inf
+        [wl.chief[0], wl.chief[1], wl.chief[2] + 1e-3, *wl.chief[3:]],  # straight above at t=0
+        [np.nan, 0, 0, 0, 0, 0],
+        [-wl.mu, 0, 0, 0, 0, 0],                           # on the larger primary
+        [1 - wl.mu, 0, 0, 0, 0, 0],                        # on the smaller primary
+        [1e300, 0, 0, 0, 0, 0],
+        wl.truth,
+    ])
+    got = gpu_cost(torch, dev, h, xs)
+    want = oracle.cost(P, xs)
+    assert want[0] == np.inf
+    assert_cost_parity(got, want)
+
+
+def test_eval_parity_c1_full_size_sampled(torch_dev):
+    """The full single-swarm workload (65,536 particles, 40 observations over
+    4000 steps) in one launch, as the benchmark runs it; the oracle checks a
+    stratified sample of particles one by one."""
+    torch, dev = torch_dev
+    wl = W.c1(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    xs = W.random_swarm(6, wl.m, wl.lo, wl.hi)
+    xs[12345] = wl.truth
+    got = gpu_cost(torch, dev, h, xs)
+    idx = np.unique(np.concatenate([np.arange(0, wl.m, 1543), [12345, wl.m - 1]]))
+    rel = assert_cost_parity(got[idx], oracle.cost(P, xs[idx]))
+    print(f"c1 sampled {len(idx)} particles, max rel err {rel:.2e}")
+
+
+def gpu_swarm_arrays(sw, m):
+    g = lambda t: t.cpu().numpy()
+    return dict(x=g(sw.x)[:, :m].T, v=g(sw.v)[:, :m].T, p=g(sw.p)[:, :m].T,
+                jp=g(sw.jp)[:m], cost=g(sw.cost)[:m])
+
+
+def assert_swarm_equal(sw, ref, m, exact_costs=False):
+    a = gpu_swarm_arrays(sw, m)
+    for f in ("x", "v", "p"):
+        assert np.array_equal(a[f], getattr(ref, f)), f
+    for f in ("jp", "cost"):
+        if exact_costs:
+            assert np.array_equal(a[f], getattr(ref, f)), f
+        else:
+            assert_cost_parity(a[f], getattr(ref, f))
+
+
+@pytest.mark.parametrize("m", [256, 300, 1])
+def test_pso_steps_bitwise(torch_dev, m):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, 17, wl.lo, wl.hi, problem=2)
+    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, 17, wl.lo, wl.hi, problem=2)
+    ref = oracle.pso_init(P, S, m)
+    sw = iod.Swarm(m, device=dev, hist_len=8)
+    iod.iod_swarm_init(h, sw, params)
+    torch.cuda.synchronize()
+    assert_swarm_equal(sw, ref, m)
+    g, jg, gi = iod.iod_swarm_best(h, sw)
+    assert gi == ref.gi.value and np.array_equal(g, ref.g)
+    hist_ref = [ref.jg.value]
+    for n_more in (1, 2, 3):
+        hist_ref += list(oracle.pso_iterate(P, S, ref, n_more))
+        iod.iod_step(h, sw, params, n_more)
+        torch.cuda.synchronize()
+        assert sw.iter == ref.iter
+        assert_swarm_equal(sw, ref, m)
+        g, jg, gi = iod.iod_swarm_best(h, sw)
+        assert gi == ref.gi.value and np.array_equal(g, ref.g), (sw.iter, gi, ref.gi.value)
+        assert abs(jg - ref.jg.value) <= COST_RTOL * abs(ref.jg.value)
+    hist = sw.hist.cpu().numpy()[:7]
+    assert np.all(np.abs(hist - hist_ref) <= COST_RTOL * np.abs(hist_ref))
+
+
+def test_pso_c0_full_run(torch_dev):
+    """The small workload end to end: 256 particles x 100 iterations."""
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    g_ref, jg_ref, hist_ref, ref = oracle.pso_solve(P, S, wl.m, wl.n_iter)
+    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    g, jg, hist = iod.iod_solve(h, params, wl.m, wl.n_iter)
+    assert np.array_equal(g, g_ref)
+    assert abs(jg - jg_ref) <= COST_RTOL * jg_ref
+    assert np.all(np.abs(hist - hist_ref) <= COST_RTOL * hist_ref)
+    assert np.all(np.diff(hist) <= 0)
+    print(f"c0: J_g {hist[0]:.4e} -> {hist[-1]:.4e}; position error "
+          f"{np.linalg.norm(g[:3] - wl.truth[:3]):.3e} LU")
+
+
+def test_solve_equals_step_and_resume_is_bitwise(torch_dev):
+    torch, dev = torch_dev
+    wl = W.c0(2)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    params = iod.pso_params(0.7, 1.5, 1.5, 3, wl.lo, wl.hi)
+    g1, j1, hist1 = iod.iod_solve(h, params, 200, 9)
+    g1b, j1b, hist1b = iod.iod_solve(h, params, 200, 9)
+    assert np.array_equal(g1, g1b) and j1 == j1b and np.array_equal(hist1, hist1b)
+    sw = iod.Swarm(200, device=dev, hist_len=10)
+    iod.iod_swarm_init(h, sw, params)
+    iod.iod_step(h, sw, params, 4)
+    iod.iod_swarm_best(h, sw)          # a best query in between changes nothing
+    iod.iod_step(h, sw, params, 5)
+    g2, j2, _ = iod.iod_swarm_best(h, sw)
+    assert np.array_equal(g1, g2) and j1 == j2
+    assert np.array_equal(sw.hist.cpu().numpy(), hist1)
+
+
+def test_degenerate_box_ties_pick_lowest_index(torch_dev):
+    """lo == hi: every particle is identical, every cost ties; the global best
+    is particle 0 and nothing moves."""
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    c = wl.chief + 1e-3
+    params = iod.pso_params(0.7, 1.5, 1.5, 0, c, c)
+    sw = iod.Swarm(700, device=dev)
+    iod.iod_swarm_init(h, sw, params)
+    iod.iod_step(h, sw, params, 3)
+    g, jg, gi = iod.iod_swarm_best(h, sw)
+    assert gi == 0 and np.array_equal(g, c)
+    assert np.all(sw.x.cpu().numpy()[:, :700] == c[:, None])
+
+
+def test_single_observation_and_chi2(torch_dev):
+    torch, dev = torch_dev
+    wl = W.tiny(0, K=1, T=0.05)
+    for mode in (0, 1):
+        P, obs = make_problem(wl, mode=mode)
+        h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h, cost_mode=mode)
+        S = oracle.Pso(0.7, 1.5, 1.5, 1, wl.lo, wl.hi)
+        g_ref, jg_ref, hist_ref, _ = oracle.pso_solve(P, S, 64, 6)
+        g, jg, hist = iod.iod_solve(h, iod.pso_params(0.7, 1.5, 1.5, 1, wl.lo, wl.hi), 64, 6)
+        assert np.array_equal(g, g_ref)
+        assert np.all(np.abs(hist - hist_ref) <= COST_RTOL * np.abs(hist_ref))
+
+
+def test_c1_full_size_iterations_properties(torch_dev):
+    """The single large swarm (65,536 particles) for a few iterations in the
+    benchmark's launch configuration: initial states and costs of sampled
+    particles match the oracle, the global best is the cost of its own state,
+    is the minimum personal best and never increases."""
+    torch, dev = torch_dev
+    wl = W.c1(0, n_iter=3)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    sw = iod.Swarm(wl.m, device=dev, hist_len=wl.n_iter + 1)
+    iod.iod_swarm_init(h, sw, params)
+    torch.cuda.synchronize()
+    a = gpu_swarm_arrays(sw, wl.m)
+    S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    ref = oracle.pso_init(P, S, 48)             # initialisation is per particle
+    assert np.array_equal(a["x"][:48], ref.x)
+    assert_cost_parity(a["jp"][:48], ref.jp)
+    iod.iod_step(h, sw, params, wl.n_iter)
+    g, jg, gi = iod.iod_swarm_best(h, sw)
+    a = gpu_swarm_arrays(sw, wl.m)
+    hist = sw.hist.cpu().numpy()
+    assert np.all(np.diff(hist) <= 0)
+    key = np.where(np.isnan(a["jp"]), np.inf, a["jp"])
+    assert jg == key.min() and gi == int(np.argmin(key))
+    assert np.array_equal(g, a["p"][gi])
+    assert_cost_parity(np.array([jg]), oracle.cost(P, g[None, :]))
