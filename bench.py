@@ -39,7 +39,7 @@ FLOP_PER_OBS = 27        # residual and cost: 24 flops + 1 sqrt + 2 atan2
 FLOP_PER_UPDATE = 50     # PSO velocity/position update of one particle
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_13175_amd", "csrc", "iod_kernels.hip")
 
 
@@ -49,16 +49,18 @@ def kernel_hash() -> str:
 
 
 def load_traffic():
-    """HBM bytes per launch of the iteration kernel from the committed
-    rocprofv3 counter summary, or None if the kernel changed since."""
+    """Calibrated HBM bytes per launch of the iteration kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE), or None if
+    the kernel source changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_sha") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def make_workload(name):
@@ -124,7 +126,6 @@ def main():
 
     import torch
     import paper_2207_13175_amd as iod
-    from paper_2207_13175_amd import __name__ as _pkg  # noqa: F401
 
     if not os.path.exists(iod.LIB_PATH):
         import __graft_entry__

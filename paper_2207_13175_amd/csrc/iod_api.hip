@@ -57,12 +57,15 @@ struct iod_handle {
     double chief[6] = {0, 0, 0, 0, 0, 0};
     std::vector<double> rc;    // [K][3] chief positions
     double *d_tab = nullptr;   // [K][TAB_W]
+    int32_t *d_ns = nullptr;   // [K]
 
     KArgs kargs() const
     {
         KArgs A;
         A.tab = d_tab;
+        A.ns = d_ns;
         A.K = K;
+        A.fast = mu == 0.0 || mu >= 0x1p-60;
         A.mode = mode;
         A.mu = mu;
         A.mu1 = mu1;
@@ -225,6 +228,8 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
     h->rc.assign(3 * (size_t)n_obs, 0.0);
 
     std::vector<double> tab((size_t)n_obs * TAB_W, 0.0);
+    std::vector<int32_t> ns32(n_obs);
+    for (int32_t k = 0; k < n_obs; ++k) ns32[k] = (int32_t)ns[k];
     for (int32_t k = 0; k < n_obs; ++k) {
         double *row = &tab[(size_t)k * TAB_W];
         row[TAB_NS] = (double)ns[k];
@@ -243,6 +248,7 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
         if (d_st) (void)hipFree(d_st);
         if (code != IOD_OK) {
             if (h->d_tab) (void)hipFree(h->d_tab);
+            if (h->d_ns) (void)hipFree(h->d_ns);
             delete h;
         }
         return code;
@@ -253,6 +259,8 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
         if (e_ != hipSuccess) return cleanup(hip_fail(e_, #expr)); \
     } while (0)
     CREATE_TRY(hipMalloc(&h->d_tab, tab.size() * sizeof(double)));
+    CREATE_TRY(hipMalloc(&h->d_ns, ns32.size() * sizeof(int32_t)));
+    CREATE_TRY(hipMemcpy(h->d_ns, ns32.data(), ns32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CREATE_TRY(hipMalloc(&d_x, 6 * sizeof(double)));
     CREATE_TRY(hipMalloc(&d_st, st.size() * sizeof(double)));
     CREATE_TRY(hipMemcpy(h->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -279,6 +287,10 @@ int iod_destroy(iod_handle *h)
         if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
         if (h->d_tab) {
             e = hipFree(h->d_tab);
+            if (e != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
+        }
+        if (h->d_ns) {
+            e = hipFree(h->d_ns);
             if (e != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
         }
     }

@@ -8,7 +8,7 @@
 namespace iodk {
 
 // One observation row of the device table, TAB_W doubles:
-//   [0] whole RK4 steps before the observation (exact integer)
+//   [0] whole RK4 steps before the observation (also in KArgs::ns as int32)
 //   [1] partial step tau (0 when the observation is on the grid)
 //   [2..4] chief position at the observation time
 //   [5..8] sin(az_obs), cos(az_obs), sin(el_obs), cos(el_obs)
@@ -27,8 +27,10 @@ constexpr int REC = 8;
 
 struct KArgs {
     const double *tab;  // device [K][TAB_W]
+    const int32_t *ns;  // device [K] whole steps before each observation
     int32_t K;
     int32_t mode;       // 0 = sum e_k^2, 1 = sum e_k
+    bool fast;          // mu == 0 or mu >= 2^-60: in-range sqrt/div allowed
     double mu, mu1;     // mu and 1 - mu
     double h, h2, h6;   // h, h/2, h/6
     double w;           // 1 / sigma^2

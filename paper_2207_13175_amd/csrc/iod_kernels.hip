@@ -25,8 +25,9 @@
 // multiply-add is explicit. The evaluation order of the right-hand side, the
 // RK4 combination, the residual and the swarm update is one fixed order
 // (written out in each function) so that a CPU implementation following the
-// same order produces the same bits; sqrt and division are the correctly
-// rounded device operations. MFMA is not used: nothing here is a dense
+// same order produces the same bits; sqrt and division are correctly
+// rounded (the hot loop runs certified in-range forms of the device
+// sequences, falling back to the full ones per step). MFMA is not used: nothing here is a dense
 // contraction; the bound is the FP64 vector ALU.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -40,11 +41,56 @@ namespace iodk {
 // Dynamics: eqs. cr3bp:x-z in the rotating barycentric frame.
 // ---------------------------------------------------------------------------
 
+// In-range forms of the device's correctly rounded FP64 sqrt and division.
+// They are the same instruction sequences the compiler emits for sqrt(x) and
+// a / b (hardware reciprocal-sqrt / reciprocal seed, one Goldschmidt step and
+// two Markstein corrections; two Newton steps and a corrected quotient)
+// without the operand rescaling and special-value fixups, which are
+// identities when x >= 2^-767 is finite and when b is normal, the quotient
+// is normal and exponent(a) - exponent(b) < 768.
+__device__ __forceinline__ double sqrt_inrange(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double hh = y * 0.5;
+    const double r = fma(-hh, g, 0.5);
+    g = fma(g, r, g);
+    hh = fma(hh, r, hh);
+    double d = fma(-g, g, x);
+    g = fma(d, hh, g);
+    d = fma(-g, g, x);
+    return fma(d, hh, g);
+}
+
+__device__ __forceinline__ double div_inrange(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    e = fma(-b, q, a);
+    return fma(e, r, q);
+}
+
 // f(s) for s = (x, y, z, vx, vy, vz):
 //   ax =  2 vy + x - (1-mu)(x+mu)/r1^3 - mu (x-(1-mu))/r2^3
 //   ay = -2 vx + y - ((1-mu)/r1^3 + mu/r2^3) y
 //   az =           - ((1-mu)/r1^3 + mu/r2^3) z
-__device__ __forceinline__ void rhs(double mu, double mu1, const double s[6], double f[6])
+// with c_j = mu_j / (r_j^2 sqrt(r_j^2)), sqrt and division correctly rounded.
+//
+// INRANGE = true uses the in-range sequences and returns whether the result
+// is certified equal to the IEEE one: c1 + c2 <= 2^600 and c1 >= 2^-700
+// (with mu = 0 or mu >= 2^-60). Any input outside the sequences' domain
+// (r_j^2 zero, denormal, below 2^-767, infinite or NaN; r_j^3 overflowing
+// or denormal) drives c_j to NaN, 0 or above 2^600, so it fails the test;
+// a passing c1 bounds r1^3 within [2^-601, 2^700], hence r2^3 <= ~2^701, so
+// both divisions have normal operands, normal quotients and exponent gaps
+// below 768, and both radicands lie in [2^-767, 2^468]. INRANGE = false is
+// the IEEE path (always certified).
+template <bool INRANGE>
+__device__ __forceinline__ bool rhs(double mu, double mu1, const double s[6], double f[6])
 {
     const double x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4];
     const double d1 = x + mu;
@@ -52,8 +98,14 @@ __device__ __forceinline__ void rhs(double mu, double mu1, const double s[6], do
     const double q = fma(z, z, y * y);
     const double r1s = fma(d1, d1, q);
     const double r2s = fma(d2, d2, q);
-    const double c1 = mu1 / (r1s * sqrt(r1s));
-    const double c2 = mu / (r2s * sqrt(r2s));
+    double c1, c2;
+    if (INRANGE) {
+        c1 = div_inrange(mu1, r1s * sqrt_inrange(r1s));
+        c2 = div_inrange(mu, r2s * sqrt_inrange(r2s));
+    } else {
+        c1 = mu1 / (r1s * sqrt(r1s));
+        c2 = mu / (r2s * sqrt(r2s));
+    }
     const double cs = c1 + c2;
     f[0] = s[3];
     f[1] = s[4];
@@ -61,39 +113,58 @@ __device__ __forceinline__ void rhs(double mu, double mu1, const double s[6], do
     f[3] = fma(-c2, d2, fma(-c1, d1, fma(2.0, vy, x)));
     f[4] = fma(-cs, y, fma(-2.0, vx, y));
     f[5] = -(cs * z);
+    return !INRANGE || (cs <= 0x1p600 && c1 >= 0x1p-700);
 }
 
-// Classical RK4 step of size h (h2 = h/2, h6 = h/6), in place. The stage sum
-// a = k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are produced, so
-// only X, a, the stage input and one derivative are live.
-__device__ __forceinline__ void rk4(double mu, double mu1, double h, double h2, double h6,
-                                    double X[6])
+// Classical RK4 step of size h (h2 = h/2, h6 = h/6) from X into Y. The stage
+// sum a = k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are produced,
+// so only X, a, the stage input and one derivative are live. Returns whether
+// every stage is certified.
+template <bool INRANGE>
+__device__ __forceinline__ bool rk4_into(double mu, double mu1, double h, double h2, double h6,
+                                         const double X[6], double Y[6])
 {
     double k[6], a[6], s[6];
-    rhs(mu, mu1, X, k);
+    bool ok = rhs<INRANGE>(mu, mu1, X, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = k[d];
         s[d] = fma(h2, k[d], X[d]);
     }
-    rhs(mu, mu1, s, k);
+    ok &= rhs<INRANGE>(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fma(2.0, k[d], a[d]);
         s[d] = fma(h2, k[d], X[d]);
     }
-    rhs(mu, mu1, s, k);
+    ok &= rhs<INRANGE>(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fma(2.0, k[d], a[d]);
         s[d] = fma(h, k[d], X[d]);
     }
-    rhs(mu, mu1, s, k);
+    ok &= rhs<INRANGE>(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = a[d] + k[d];
-        X[d] = fma(h6, a[d], X[d]);
+        Y[d] = fma(h6, a[d], X[d]);
     }
+    return ok;
+}
+
+// One RK4 step in place. The step runs with the in-range sequences; if any
+// lane of the wave is not certified, the wave repeats the step from X on the
+// IEEE path. Both give the same bits wherever the first is certified, so
+// the result is always that of correctly rounded sqrt and division.
+__device__ __forceinline__ void rk4(double mu, double mu1, bool fast, double h, double h2,
+                                    double h6, double X[6])
+{
+    double Y[6];
+    bool ok = false;
+    if (fast) ok = rk4_into<true>(mu, mu1, h, h2, h6, X, Y);
+    if (!__all(ok)) rk4_into<false>(mu, mu1, h, h2, h6, X, Y);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = Y[d];
 }
 
 // Walk the observation schedule: advance X on the grid, and at each
@@ -101,7 +172,8 @@ __device__ __forceinline__ void rk4(double mu, double mu1, double h, double h2, 
 // when the time is off the grid) to `obs(row, S)`. Every thread of the
 // workgroup must call this (it stages the table through LDS with barriers).
 template <class Obs>
-__device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, Obs &obs)
+__device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, int32_t *lds_ns,
+                                     Obs &obs)
 {
     int32_t step = 0;
     for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
@@ -109,16 +181,17 @@ __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, O
         __syncthreads();
         for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
             lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
+        for (int32_t j = threadIdx.x; j < nk; j += blockDim.x) lds_ns[j] = A.ns[k0 + j];
         __syncthreads();
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
-            const int32_t target = __builtin_amdgcn_readfirstlane((int32_t)row[TAB_NS]);
-            for (; step < target; ++step) rk4(A.mu, A.mu1, A.h, A.h2, A.h6, X);
+            const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
+            for (; step < target; ++step) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
             const double tau = row[TAB_TAU];
             double S[6];
 #pragma unroll
             for (int d = 0; d < 6; ++d) S[d] = X[d];
-            if (tau != 0.0) rk4(A.mu, A.mu1, tau, 0.5 * tau, tau / 6.0, S);
+            if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, S);
             obs(row, S);
         }
     }
@@ -167,13 +240,14 @@ struct CostAcc {
     }
 };
 
-__device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], double *lds)
+__device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], double *lds,
+                                            int32_t *lds_ns)
 {
     double X[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = x0[d];
     CostAcc acc{0.0, A.w, A.mode};
-    walk(A, X, lds, acc);
+    walk(A, X, lds, lds_ns, acc);
     return acc.J;
 }
 
@@ -345,12 +419,13 @@ __global__ __launch_bounds__(BS) void k_propagate(KArgs A, const double *__restr
                                                   double *__restrict__ states)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool valid = i < m;
     double X[6];
     load_state(x, ld, valid ? i : m - 1, X);
     StoreStates obs{states, ld, i, 0, valid};
-    walk(A, X, lds, obs);
+    walk(A, X, lds, lds_ns, obs);
 }
 
 __global__ __launch_bounds__(BS) void k_predict(KArgs A, const double *__restrict__ x,
@@ -358,23 +433,25 @@ __global__ __launch_bounds__(BS) void k_predict(KArgs A, const double *__restric
                                                 double *__restrict__ angles)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool valid = i < m;
     double X[6];
     load_state(x, ld, valid ? i : m - 1, X);
     StoreAngles obs{angles, ld, i, 0, valid};
-    walk(A, X, lds, obs);
+    walk(A, X, lds, lds_ns, obs);
 }
 
 __global__ __launch_bounds__(BS) void k_eval(KArgs A, const double *__restrict__ x, int64_t ld,
                                              int64_t m, double *__restrict__ cost)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool valid = i < m;
     double X[6];
     load_state(x, ld, valid ? i : m - 1, X);
-    const double J = eval_cost(A, X, lds);
+    const double J = eval_cost(A, X, lds, lds_ns);
     if (valid) cost[i] = J;
 }
 
@@ -382,6 +459,7 @@ __global__ __launch_bounds__(BS) void k_eval(KArgs A, const double *__restrict__
 __global__ __launch_bounds__(BS) void k_swarm_init(KArgs A, PsoArgs P, SwarmArgs S)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
     __shared__ double red[2 * (BS / 64)];
     __shared__ double wst[6];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -393,7 +471,7 @@ __global__ __launch_bounds__(BS) void k_swarm_init(KArgs A, PsoArgs P, SwarmArgs
     double X[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = P.lo[d] + (P.hi[d] - P.lo[d]) * u01(u[d]);
-    const double J = eval_cost(A, X, lds);
+    const double J = eval_cost(A, X, lds, lds_ns);
     if (valid) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
@@ -417,6 +495,7 @@ __global__ __launch_bounds__(BS) void k_swarm_init(KArgs A, PsoArgs P, SwarmArgs
 __global__ __launch_bounds__(BS) void k_swarm_iter(KArgs A, PsoArgs P, SwarmArgs S, int64_t n)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
     __shared__ double red[2 * (BS / 64)];
     __shared__ double wst[6];
     double *slots = S.work;
@@ -446,7 +525,7 @@ __global__ __launch_bounds__(BS) void k_swarm_iter(KArgs A, PsoArgs P, SwarmArgs
     double jp = S.jp[j];
     double J;
     if (n >= 2)
-        J = eval_cost(A, X, lds);
+        J = eval_cost(A, X, lds, lds_ns);
     else
         J = S.cost[j];
     const bool better = cost_key(J) < cost_key(jp);

@@ -313,3 +313,27 @@ def test_c1_full_size_iterations_properties(torch_dev):
     assert jg == key.min() and gi == int(np.argmin(key))
     assert np.array_equal(g, a["p"][gi])
     assert_cost_parity(np.array([jg]), oracle.cost(P, g[None, :]))
+
+
+@pytest.mark.parametrize("mu", [0.0, 1e-30, 0.5, W.MU_EARTH_MOON])
+def test_eval_parity_mass_parameter_range(torch_dev, mu):
+    """Endpoints of the mass parameter (mu = 0 is the Kepler problem; a tiny
+    mu takes the full IEEE sqrt/division path in every step) and a deputy
+    swinging close past the smaller primary."""
+    torch, dev = torch_dev
+    wl = W.tiny(3, K=6, T=0.6)
+    P0 = oracle.Problem(mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((wl.K, 2)))
+    obs = oracle.predict(P0, wl.truth) + wl.noise
+    P = P0.with_angles(obs)
+    h = iod.iod_create(mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    xs = W.random_swarm(9, 130, wl.lo, wl.hi)
+    xs[5] = [1 - mu + 0.01, 0.0, 0.0, 0.0, 0.9, 0.0]       # 0.01 LU from the smaller primary
+    xs[6] = [1 - mu + 1e-4, 0.0, 1e-4, 0.0, 2.0, 0.0]      # grazing
+    assert_cost_parity(gpu_cost(torch, dev, h, xs), oracle.cost(P, xs))
+    x = to_dev(torch, dev, xs)
+    st = torch.zeros((wl.K, 6, x.shape[1]), dtype=torch.float64, device=dev)
+    iod.iod_propagate(h, x, len(xs), st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    for i in (0, 5, 6, 77):
+        assert np.array_equal(got[:, :, i], oracle.propagate(mu, wl.h, xs[i], wl.t)), i
