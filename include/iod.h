@@ -74,8 +74,22 @@ typedef struct {
     double hi[6];
 } iod_pso_params;
 
+/* Launch configuration of the swarm kernels (see iod_set_config,
+ * iod_batch_set_config, iod_batch_autotune). Results do not depend on it. */
+typedef struct {
+    int32_t block;     /* threads per workgroup: 64, 128 or 256; 0 = default (256) */
+    int32_t order;     /* batches: IOD_ORDER_LONGEST_FIRST (default) or IOD_ORDER_PROBLEM */
+    int32_t graph;     /* iod_solve / iod_batch_solve: 1 = replay the iteration launches
+                          from one captured hipGraph, 0 = launch them directly */
+    int32_t reserved;  /* must be 0 */
+} iod_launch_config;
+
+#define IOD_ORDER_LONGEST_FIRST 0 /* workgroups of problems with more RK4 steps dispatch first */
+#define IOD_ORDER_PROBLEM 1       /* workgroups in problem order */
+
 /* Swarm state in caller-owned device memory. Fill the pointers, ld and m,
- * then call iod_swarm_init; the library keeps `iter` (iterations done). */
+ * then call iod_swarm_init; the library keeps `iter` (iterations done) and
+ * `block` (the workgroup size fixed at initialisation). */
 typedef struct {
     double *x;        /* device [6][ld] current positions */
     double *v;        /* device [6][ld] velocities */
@@ -88,7 +102,11 @@ typedef struct {
     int64_t ld;       /* leading dimension, ld >= m */
     int64_t m;        /* particles, >= 1 */
     int64_t iter;     /* iterations completed since iod_swarm_init (set by the library) */
+    int32_t block;    /* workgroup size used by this swarm (set by iod_swarm_init) */
+    int32_t reserved;
 } iod_swarm;
+
+typedef struct iod_batch iod_batch;
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int iod_version(void);
@@ -129,6 +147,11 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
  * the device before freeing. */
 int iod_destroy(iod_handle *h);
 
+/* Launch configuration for this handle's swarm kernels (host only). A
+ * swarm keeps the workgroup size it was initialised with. */
+int iod_set_config(iod_handle *h, const iod_launch_config *cfg);
+int iod_get_config(const iod_handle *h, iod_launch_config *cfg);
+
 /* Number of observations K of a handle, or a negative code. */
 int32_t iod_num_obs(const iod_handle *h);
 
@@ -161,8 +184,8 @@ int iod_predict(iod_handle *h, const double *x, int64_t ld, int64_t m,
 int iod_eval_swarm(iod_handle *h, const double *x, int64_t ld, int64_t m,
                    double *cost, void *stream);
 
-/* Doubles needed in iod_swarm.work for a swarm of m particles (>= 1), or a
- * negative code. */
+/* Doubles needed in iod_swarm.work for a swarm of m particles (>= 1) under
+ * any launch configuration, or a negative code. */
 int64_t iod_swarm_work_len(int64_t m);
 
 /* Algorithm 1 initialisation: x uniform in [lo, hi] from Philox4x64-10
@@ -196,6 +219,80 @@ int iod_swarm_best(iod_handle *h, iod_swarm *s, double best_state[6], double *be
  * iteration. Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
               double best_state[6], double *best_cost, double *history);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent problems with uneven observation counts, arcs  */
+/* and swarm sizes, advanced together, one kernel launch per iteration for  */
+/* the whole batch.                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Create a batch of n_problems problems, each as in iod_create.
+ *   mu            host [P]
+ *   chief_states  host [P][6]
+ *   obs_offsets   host [P + 1], obs_offsets[0] = 0, non-decreasing; problem p
+ *                 owns observations obs_offsets[p] .. obs_offsets[p + 1] - 1
+ *                 (1 to IOD_MAX_OBS of them)
+ *   obs_times     host [obs_offsets[P]] (per problem as in iod_schedule)
+ *   obs_angles    host [obs_offsets[P]][2]
+ *   sigma         host [P]
+ *   opt           host [P] or NULL (defaults for every problem)
+ * Host arrays are copied. Synchronises the device.
+ * Errors: IOD_EINVAL (message names the problem), IOD_ENOMEM, IOD_EDEVICE. */
+int iod_create_batch(int32_t n_problems, const double *mu, const double *chief_states,
+                     const int64_t *obs_offsets, const double *obs_times,
+                     const double *obs_angles, const double *sigma, const iod_options *opt,
+                     iod_batch **out);
+
+/* Release a batch (NULL is accepted). Synchronises the device. */
+int iod_batch_destroy(iod_batch *b);
+
+/* Number of problems, or a negative code. */
+int32_t iod_batch_size(const iod_batch *b);
+
+/* RK4 steps of one fitness evaluation of problem p (whole steps to the last
+ * observation, plus one if it is off the grid), or a negative code. */
+int64_t iod_batch_steps(const iod_batch *b, int32_t p);
+
+/* Launch configuration of the batch (host only). */
+int iod_batch_set_config(iod_batch *b, const iod_launch_config *cfg);
+int iod_batch_get_config(const iod_batch *b, iod_launch_config *cfg);
+
+/* Column offsets of a batched swarm: problem p with m[p] >= 0 particles
+ * owns columns off[p] .. off[p] + m[p] - 1 of a [6][ld] array, where
+ * off[p] = sum over q < p of m[q] rounded up to a multiple of 64.
+ *   m host [P]; off host [P + 1] (off[P] is the least valid ld)
+ * Returns off[P], or a negative code. */
+int64_t iod_batch_offsets(const iod_batch *b, const int64_t *m, int64_t *off);
+
+/* Fitness of every problem's particles (as iod_eval_swarm, per problem).
+ *   x     device [6][ld], columns per iod_batch_offsets
+ *   m     host [P] particles per problem (0 allowed)
+ *   cost  device [ld]
+ * Synchronises `stream` (the launch uses temporary device tables).
+ * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                   void *stream);
+
+/* Solve every problem with its own swarm: params host [P] (set
+ * params[p].problem = p, or any distinct values, for independent random
+ * streams), m host [P] >= 1 particles, n_iter iterations of Algorithm 1 for
+ * all. Outputs (host): best_states [P][6], best_costs [P], and history
+ * [P][n_iter + 1] or NULL. Problem p's results are bit-identical to
+ * iod_solve on the same problem with params[p] and m[p]. Synchronous.
+ * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
+                    double *best_states, double *best_costs, double *history);
+
+/* Time trial_iters iterations of the batch under each candidate launch
+ * configuration (workgroup size 64/128/256 x longest-first/problem order x
+ * graph on/off), keep the fastest as the batch's configuration and return it
+ * in *chosen. If ms_per_iter is given it receives the mean time per
+ * iteration of each candidate, in the order block-major, then order, then
+ * graph (12 values); *n_candidates receives the count. Synchronous.
+ * Errors: as iod_batch_solve. */
+int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                       int64_t trial_iters, iod_launch_config *chosen, double *ms_per_iter,
+                       int32_t *n_candidates);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,17 @@ class iod_swarm(C.Structure):
     _fields_ = [("x", C.c_void_p), ("v", C.c_void_p), ("p", C.c_void_p),
                 ("jp", C.c_void_p), ("cost", C.c_void_p), ("work", C.c_void_p),
                 ("hist", C.c_void_p), ("hist_len", C.c_int64), ("ld", C.c_int64),
-                ("m", C.c_int64), ("iter", C.c_int64)]
+                ("m", C.c_int64), ("iter", C.c_int64), ("block", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class iod_launch_config(C.Structure):
+    _fields_ = [("block", C.c_int32), ("order", C.c_int32), ("graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+IOD_ORDER_LONGEST_FIRST = 0
+IOD_ORDER_PROBLEM = 1
 
 
 # name -> (restype, argtypes); the exported C ABI
@@ -73,6 +83,20 @@ _SIGNATURES = {
     "iod_step": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), C.POINTER(iod_pso_params), C.c_int64, C.c_void_p]),
     "iod_swarm_best": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), _D, _D, _I64, C.c_void_p]),
     "iod_solve": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), C.c_int64, C.c_int64, _D, _D, _D]),
+    "iod_set_config": (C.c_int, [C.c_void_p, C.POINTER(iod_launch_config)]),
+    "iod_get_config": (C.c_int, [C.c_void_p, C.POINTER(iod_launch_config)]),
+    "iod_create_batch": (C.c_int, [C.c_int32, _D, _D, _I64, _D, _D, _D, C.POINTER(iod_options),
+                                   C.POINTER(C.c_void_p)]),
+    "iod_batch_destroy": (C.c_int, [C.c_void_p]),
+    "iod_batch_size": (C.c_int32, [C.c_void_p]),
+    "iod_batch_steps": (C.c_int64, [C.c_void_p, C.c_int32]),
+    "iod_batch_set_config": (C.c_int, [C.c_void_p, C.POINTER(iod_launch_config)]),
+    "iod_batch_get_config": (C.c_int, [C.c_void_p, C.POINTER(iod_launch_config)]),
+    "iod_batch_offsets": (C.c_int64, [C.c_void_p, _I64, _I64]),
+    "iod_batch_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_void_p, C.c_void_p]),
+    "iod_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64, _D, _D, _D]),
+    "iod_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
+                                     C.POINTER(iod_launch_config), _D, C.POINTER(C.c_int32)]),
 }
 
 _lib = None
@@ -229,7 +253,7 @@ class Swarm:
         self.s = iod_swarm(self.x.data_ptr(), self.v.data_ptr(), self.p.data_ptr(),
                            self.jp.data_ptr(), self.cost.data_ptr(), self.work.data_ptr(),
                            self.hist.data_ptr() if hist_len > 0 else None, int(hist_len),
-                           self.ld, self.m, -1)
+                           self.ld, self.m, -1, 0, 0)
 
     @property
     def iter(self):
@@ -263,3 +287,117 @@ def iod_solve(handle: Handle, params: iod_pso_params, m, n_iter):
     _check(lib().iod_solve(handle.ptr, C.byref(params), int(m), int(n_iter), _dp(st), C.byref(J),
                            _dp(hist)))
     return st, J.value, hist
+
+
+def iod_set_config(handle: Handle, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=0):
+    _check(lib().iod_set_config(handle.ptr, C.byref(iod_launch_config(block, order, graph, 0))))
+
+
+def iod_get_config(handle: Handle) -> iod_launch_config:
+    c = iod_launch_config()
+    _check(lib().iod_get_config(handle.ptr, C.byref(c)))
+    return c
+
+
+# ----------------------------------------------------------------------------
+# Batches
+# ----------------------------------------------------------------------------
+
+class Batch:
+    """Owns an iod_batch; destroyed with the object (or by iod_batch_destroy)."""
+
+    def __init__(self, ptr, P, K):
+        self.ptr = ptr
+        self.P = P
+        self.K = K
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.iod_batch_destroy(self.ptr)
+            self.ptr = None
+
+
+def iod_create_batch(mu, chief_states, obs_times, obs_angles, sigma, h=None, cost_mode=None):
+    """Lists per problem: mu [P], chief_states [P][6], obs_times [P][K_p],
+    obs_angles [P][K_p][2], sigma [P]; h and cost_mode scalars or per problem."""
+    P = len(mu)
+    K = np.array([len(t) for t in obs_times], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(K)]).astype(np.int64)
+    t = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).ravel() for x in obs_times]))
+    ang = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1)
+                                               for a in obs_angles]))
+    mu_a = np.ascontiguousarray(mu, dtype=np.float64)
+    ch = np.ascontiguousarray(chief_states, dtype=np.float64).reshape(P, 6)
+    sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (P,)))
+    opts = None
+    if h is not None or cost_mode is not None:
+        hh = np.broadcast_to(np.asarray(1e-3 if h is None else h, dtype=np.float64), (P,))
+        cm = np.broadcast_to(np.asarray(0 if cost_mode is None else cost_mode), (P,))
+        opts = (iod_options * P)(*[iod_options(float(hh[p]), int(cm[p]), 0) for p in range(P)])
+    out = C.c_void_p()
+    _check(lib().iod_create_batch(P, _dp(mu_a), _dp(ch), off.ctypes.data_as(_I64), _dp(t), _dp(ang),
+                                  _dp(sg), opts, C.byref(out)))
+    return Batch(out, P, K)
+
+
+def iod_batch_destroy(batch: Batch):
+    if batch.ptr:
+        rc = lib().iod_batch_destroy(batch.ptr)
+        batch.ptr = None
+        _check(rc)
+
+
+def iod_batch_steps(batch: Batch):
+    return np.array([_check(lib().iod_batch_steps(batch.ptr, p)) for p in range(batch.P)],
+                    dtype=np.int64)
+
+
+def iod_batch_set_config(batch: Batch, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=1):
+    _check(lib().iod_batch_set_config(batch.ptr, C.byref(iod_launch_config(block, order, graph, 0))))
+
+
+def iod_batch_get_config(batch: Batch) -> iod_launch_config:
+    c = iod_launch_config()
+    _check(lib().iod_batch_get_config(batch.ptr, C.byref(c)))
+    return c
+
+
+def iod_batch_offsets(batch: Batch, m):
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    off = np.empty(batch.P + 1, dtype=np.int64)
+    _check(lib().iod_batch_offsets(batch.ptr, m.ctypes.data_as(_I64), off.ctypes.data_as(_I64)))
+    return off
+
+
+def iod_batch_eval(batch: Batch, x, m, cost, stream=None):
+    """x: [6, ld] with columns per iod_batch_offsets -> cost [ld]."""
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    ld = x.shape[1]
+    _check(lib().iod_batch_eval(batch.ptr, _dev(x, (6, ld)), ld, m.ctypes.data_as(_I64),
+                                _dev(cost, (ld,)), _stream(stream)))
+
+
+def _params_array(params):
+    return (iod_pso_params * len(params))(*params)
+
+
+def iod_batch_solve(batch: Batch, params, m, n_iter, history=True):
+    """(best states [P, 6], best costs [P], history [P, n_iter + 1] or None)."""
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    st = np.empty((batch.P, 6))
+    J = np.empty(batch.P)
+    hist = np.empty((batch.P, int(n_iter) + 1)) if history else None
+    _check(lib().iod_batch_solve(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
+                                 int(n_iter), _dp(st), _dp(J), _dp(hist) if history else None))
+    return st, J, hist
+
+
+def iod_batch_autotune(batch: Batch, params, m, trial_iters=4):
+    """(chosen iod_launch_config, ms per iteration of the 12 candidates)."""
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    cfg = iod_launch_config()
+    ms = np.empty(12)
+    n = C.c_int32()
+    _check(lib().iod_batch_autotune(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
+                                    int(trial_iters), C.byref(cfg), _dp(ms), C.byref(n)))
+    return cfg, ms[:n.value]

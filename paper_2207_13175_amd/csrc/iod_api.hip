@@ -1,14 +1,17 @@
 // iod_api.hip -- host side of libiod: the C ABI declared in include/iod.h.
 // Argument validation, the observation schedule, per-problem device tables
-// (chief ephemeris and observed-angle sines/cosines) and the launch sequence
-// of the particle swarm (Algorithm 1 of Zuehlke et al., AAS 22-770).
+// (chief ephemeris and observed-angle sines/cosines), work lists and the
+// launch sequence of the particle swarm (Algorithm 1 of Zuehlke et al.,
+// AAS 22-770), for one problem or a batch of independent problems.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "../../include/iod.h"
@@ -35,9 +38,9 @@ int hip_fail(hipError_t e, const char *what)
                 hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
@@ -48,51 +51,118 @@ bool finite6(const double *v)
     return true;
 }
 
-}  // namespace
+constexpr int64_t MAX_M = (int64_t)1 << 40;
+constexpr int DEFAULT_BLOCK = 256;
 
-struct iod_handle {
-    int device = 0;
-    double mu = 0, mu1 = 0, h = 0, sigma = 0, w = 0;
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round64(int64_t a) { return ceil_div(a, 64) * 64; }
+
+// Host-side description of one problem, validated, with its observation
+// table rows (chief positions filled in on the device).
+struct HostProblem {
+    double mu = 0, h = 0, sigma = 0;
     int32_t K = 0, mode = 0;
     double chief[6] = {0, 0, 0, 0, 0, 0};
-    std::vector<double> rc;    // [K][3] chief positions
-    double *d_tab = nullptr;   // [K][TAB_W]
-    int32_t *d_ns = nullptr;   // [K]
-
-    KArgs kargs() const
-    {
-        KArgs A;
-        A.tab = d_tab;
-        A.ns = d_ns;
-        A.K = K;
-        A.fast = mu == 0.0 || mu >= 0x1p-60;
-        A.mode = mode;
-        A.mu = mu;
-        A.mu1 = mu1;
-        A.h = h;
-        A.h2 = 0.5 * h;
-        A.h6 = h / 6.0;
-        A.w = w;
-        return A;
-    }
+    std::vector<double> tab;    // [K][TAB_W]
+    std::vector<int32_t> ns;    // [K]
+    int64_t steps = 0;          // RK4 steps of one evaluation
 };
 
-namespace {
-
-int check_handle(iod_handle *h)
+int check_config(const iod_launch_config *c)
 {
-    if (!h) return fail(IOD_EINVAL, "null handle");
-    HIP_TRY(hipSetDevice(h->device));
+    if (!c) return fail(IOD_EINVAL, "null iod_launch_config");
+    if (c->block != 0 && c->block != 64 && c->block != 128 && c->block != 256)
+        return fail(IOD_EINVAL, "block must be 0, 64, 128 or 256");
+    if (c->order != IOD_ORDER_LONGEST_FIRST && c->order != IOD_ORDER_PROBLEM)
+        return fail(IOD_EINVAL, "unknown order %d", c->order);
+    if (c->graph != 0 && c->graph != 1) return fail(IOD_EINVAL, "graph must be 0 or 1");
+    if (c->reserved != 0) return fail(IOD_EINVAL, "reserved must be 0");
     return IOD_OK;
 }
 
-int check_swarm_view(const double *x, int64_t ld, int64_t m, const void *out)
+int block_of(const iod_launch_config &c) { return c.block ? c.block : DEFAULT_BLOCK; }
+
+}  // namespace
+
+extern "C" int iod_schedule(const double *t, int32_t n_obs, double h, int64_t *nsteps, double *tau);
+
+namespace {
+
+int make_problem(double mu, const double *chief, const double *t, const double *ang, int32_t K,
+                 double sigma, const iod_options *opt, HostProblem &P)
 {
-    if (m < 0) return fail(IOD_EINVAL, "m = %lld < 0", (long long)m);
-    if (ld < m || ld < 1) return fail(IOD_EINVAL, "ld = %lld must be >= max(m, 1)", (long long)ld);
-    if (m > (int64_t)0x7fffffff * BS) return fail(IOD_EINVAL, "m too large");
-    if (m > 0 && (!x || !out)) return fail(IOD_EINVAL, "null device pointer");
+    if (!chief || !t || !ang) return fail(IOD_EINVAL, "null host pointer");
+    if (!std::isfinite(mu) || mu < 0.0 || mu > 0.5) return fail(IOD_EINVAL, "mu must lie in [0, 0.5]");
+    if (!finite6(chief)) return fail(IOD_EINVAL, "non-finite chief state");
+    if (!(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(IOD_EINVAL, "sigma must be positive and finite");
+    if (K < 1 || K > IOD_MAX_OBS) return fail(IOD_EINVAL, "n_obs = %d out of range", K);
+    iod_options o{1e-3, IOD_COST_PAPER, 0};
+    if (opt) o = *opt;
+    if (o.cost_mode != IOD_COST_PAPER && o.cost_mode != IOD_COST_CHI2)
+        return fail(IOD_EINVAL, "unknown cost_mode %d", o.cost_mode);
+    if (o.reserved != 0) return fail(IOD_EINVAL, "options.reserved must be 0");
+    for (int32_t k = 0; k < 2 * K; ++k)
+        if (!std::isfinite(ang[k])) return fail(IOD_EINVAL, "non-finite obs_angles[%d]", k);
+    std::vector<int64_t> ns(K);
+    std::vector<double> tau(K);
+    int rc = iod_schedule(t, K, o.h, ns.data(), tau.data());
+    if (rc != IOD_OK) return rc;
+    P.mu = mu;
+    P.h = o.h;
+    P.sigma = sigma;
+    P.K = K;
+    P.mode = o.cost_mode;
+    std::memcpy(P.chief, chief, sizeof P.chief);
+    P.tab.assign((size_t)K * TAB_W, 0.0);
+    P.ns.resize(K);
+    for (int32_t k = 0; k < K; ++k) {
+        double *row = &P.tab[(size_t)k * TAB_W];
+        P.ns[k] = (int32_t)ns[k];
+        row[TAB_NS] = (double)ns[k];
+        row[TAB_TAU] = tau[k];
+        row[TAB_SA] = std::sin(ang[2 * k]);
+        row[TAB_CA] = std::cos(ang[2 * k]);
+        row[TAB_SB] = std::sin(ang[2 * k + 1]);
+        row[TAB_CB] = std::cos(ang[2 * k + 1]);
+    }
+    P.steps = ns[K - 1] + (tau[K - 1] != 0.0 ? 1 : 0);
     return IOD_OK;
+}
+
+KArgs kargs_of(const HostProblem &P, const double *d_tab, const int32_t *d_ns)
+{
+    KArgs A;
+    A.tab = d_tab;
+    A.ns = d_ns;
+    A.K = P.K;
+    A.mode = P.mode;
+    A.fast = P.mu == 0.0 || P.mu >= 0x1p-60;
+    A.mu = P.mu;
+    A.mu1 = 1.0 - P.mu;
+    A.h = P.h;
+    A.h2 = 0.5 * P.h;
+    A.h6 = P.h / 6.0;
+    A.w = 1.0 / (P.sigma * P.sigma);
+    return A;
+}
+
+ProbDesc desc_of(const KArgs &A, const double chief[6], const iod_pso_params *p)
+{
+    ProbDesc D;
+    std::memset(&D, 0, sizeof D);
+    D.k = A;
+    std::memcpy(D.chief, chief, sizeof D.chief);
+    if (p) {
+        D.omega = p->omega;
+        D.eta1 = p->eta1;
+        D.eta2 = p->eta2;
+        std::memcpy(D.lo, p->lo, sizeof D.lo);
+        std::memcpy(D.hi, p->hi, sizeof D.hi);
+        D.seed = p->seed;
+        D.problem = p->problem;
+    }
+    return D;
 }
 
 int check_pso(const iod_pso_params *p)
@@ -106,19 +176,106 @@ int check_pso(const iod_pso_params *p)
     return IOD_OK;
 }
 
-PsoArgs pso_args(const iod_pso_params *p)
-{
-    PsoArgs P;
-    P.omega = p->omega;
-    P.eta1 = p->eta1;
-    P.eta2 = p->eta2;
-    P.seed = p->seed;
-    P.problem = p->problem;
-    for (int d = 0; d < 6; ++d) {
-        P.lo[d] = p->lo[d];
-        P.hi[d] = p->hi[d];
+// RAII device buffers for the synchronous entry points.
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
     }
-    return P;
+};
+
+struct Stream {
+    hipStream_t s = nullptr;
+    ~Stream()
+    {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+// Runs the iteration launches n0 + 1 .. n0 + n_iter, directly or as one
+// captured graph.
+template <class F>
+int run_iterations(hipStream_t st, bool graph, int64_t n0, int64_t n_iter, F launch_one)
+{
+    if (!graph || n_iter == 0) {
+        for (int64_t j = 1; j <= n_iter; ++j) HIP_TRY(launch_one(n0 + j));
+        return IOD_OK;
+    }
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int64_t j = 1; j <= n_iter && le == hipSuccess; ++j) le = launch_one(n0 + j);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "iteration launch under capture");
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, st);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraph instantiate/launch");
+    return IOD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single problem
+// ---------------------------------------------------------------------------
+
+struct iod_handle {
+    int device = 0;
+    HostProblem P;
+    double *d_tab = nullptr;   // [K][TAB_W]
+    int32_t *d_ns = nullptr;   // [K]
+    std::vector<double> rc;    // [K][3] chief positions
+    iod_launch_config cfg{0, IOD_ORDER_LONGEST_FIRST, 0, 0};
+
+    KArgs kargs() const { return kargs_of(P, d_tab, d_ns); }
+};
+
+struct iod_batch {
+    int device = 0;
+    int32_t P = 0;
+    std::vector<HostProblem> probs;
+    std::vector<int64_t> tab_off;  // per problem, rows
+    double *d_tab = nullptr;       // concatenated [sum K][TAB_W]
+    int32_t *d_ns = nullptr;       // concatenated [sum K]
+    iod_launch_config cfg{0, IOD_ORDER_LONGEST_FIRST, 1, 0};
+
+    KArgs kargs(int32_t p) const
+    {
+        return kargs_of(probs[p], d_tab + tab_off[p] * TAB_W, d_ns + tab_off[p]);
+    }
+};
+
+namespace {
+
+int check_handle(iod_handle *h)
+{
+    if (!h) return fail(IOD_EINVAL, "null handle");
+    HIP_TRY(hipSetDevice(h->device));
+    return IOD_OK;
+}
+
+int check_batch(iod_batch *b)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    HIP_TRY(hipSetDevice(b->device));
+    return IOD_OK;
+}
+
+int check_swarm_view(const double *x, int64_t ld, int64_t m, const void *out)
+{
+    if (m < 0) return fail(IOD_EINVAL, "m = %lld < 0", (long long)m);
+    if (ld < m || ld < 1) return fail(IOD_EINVAL, "ld = %lld must be >= max(m, 1)", (long long)ld);
+    if (m > MAX_M) return fail(IOD_EINVAL, "m too large");
+    if (m > 0 && (!x || !out)) return fail(IOD_EINVAL, "null device pointer");
+    return IOD_OK;
 }
 
 int check_swarm(const iod_swarm *s, bool need_init)
@@ -126,37 +283,51 @@ int check_swarm(const iod_swarm *s, bool need_init)
     if (!s) return fail(IOD_EINVAL, "null iod_swarm");
     if (s->m < 1) return fail(IOD_EINVAL, "swarm m = %lld < 1", (long long)s->m);
     if (s->ld < s->m) return fail(IOD_EINVAL, "swarm ld < m");
-    if (s->m > (int64_t)0x7fffffff * BS) return fail(IOD_EINVAL, "m too large");
+    if (s->m > MAX_M) return fail(IOD_EINVAL, "m too large");
     if (!s->x || !s->v || !s->p || !s->jp || !s->cost || !s->work)
         return fail(IOD_EINVAL, "null swarm device pointer");
     if (s->hist_len < 0) return fail(IOD_EINVAL, "hist_len < 0");
     if (s->hist_len > 0 && !s->hist) return fail(IOD_EINVAL, "hist_len > 0 with null hist");
-    if (need_init && s->iter < 0) return fail(IOD_ESTATE, "swarm not initialised");
+    if (need_init) {
+        if (s->iter < 0) return fail(IOD_ESTATE, "swarm not initialised");
+        if (s->block != 64 && s->block != 128 && s->block != 256)
+            return fail(IOD_ESTATE, "swarm block %d invalid (not initialised?)", s->block);
+    }
     return IOD_OK;
 }
 
-SwarmArgs swarm_args(const iod_swarm *s)
+// Launch view of a caller-owned single-problem swarm.
+void single_view(const iod_handle *h, const iod_swarm *s, const iod_pso_params *p, ProbDesc &D,
+                 SwarmArrays &B)
 {
-    SwarmArgs S;
-    S.x = s->x;
-    S.v = s->v;
-    S.p = s->p;
-    S.jp = s->jp;
-    S.cost = s->cost;
-    S.work = s->work;
-    S.hist = s->hist_len > 0 ? s->hist : nullptr;
-    S.hist_len = s->hist_len;
-    S.ld = s->ld;
-    S.m = s->m;
-    S.nslots = num_slots(s->m);
-    return S;
+    const int64_t nslots = ceil_div(s->m, s->block);
+    D = desc_of(h->kargs(), h->P.chief, p);
+    D.hist = s->hist_len > 0 ? s->hist : nullptr;
+    D.hist_len = s->hist_len;
+    D.m = s->m;
+    D.off = 0;
+    D.slot_off = 0;
+    D.nslots = nslots;
+    D.block = s->block;
+    B.desc = nullptr;
+    B.work = nullptr;
+    B.x = s->x;
+    B.v = s->v;
+    B.p = s->p;
+    B.jp = s->jp;
+    B.cost = s->cost;
+    B.slots = s->work;
+    B.recs = s->work + 2 * nslots * REC;
+    B.ld = s->ld;
+    B.total_slots = nslots;
+    B.nprob = 1;
 }
 
 }  // namespace
 
 extern "C" {
 
-int iod_version(void) { return 10000; }
+int iod_version(void) { return 10100; }
 
 const char *iod_last_error(void) { return g_err; }
 
@@ -171,8 +342,8 @@ int iod_schedule(const double *t, int32_t n_obs, double h, int64_t *nsteps, doub
         if (k > 0 && !(tk > t[k - 1]))
             return fail(IOD_EINVAL, "obs_times not strictly increasing at %d", k);
         const double q = tk / h;
-        if (q > 2147483647.0)
-            return fail(IOD_EINVAL, "obs_times[%d]/h exceeds 2^31 - 1 steps", k);
+        if (q > 2147483646.0)
+            return fail(IOD_EINVAL, "obs_times[%d]/h exceeds 2^31 - 2 steps", k);
         // nearest grid point, accepted within 1e-9 h
         const int64_t near = (int64_t)std::floor(q + 0.5);
         if (std::fabs(tk - (double)near * h) <= 1e-9 * h) {
@@ -193,89 +364,37 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
 {
     if (!out) return fail(IOD_EINVAL, "null out");
     *out = nullptr;
-    if (!chief_state || !obs_times || !obs_angles) return fail(IOD_EINVAL, "null host pointer");
-    if (!std::isfinite(mu) || mu < 0.0 || mu > 0.5) return fail(IOD_EINVAL, "mu must lie in [0, 0.5]");
-    if (!finite6(chief_state)) return fail(IOD_EINVAL, "non-finite chief state");
-    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(IOD_EINVAL, "sigma must be positive and finite");
-    if (n_obs < 1 || n_obs > IOD_MAX_OBS) return fail(IOD_EINVAL, "n_obs = %d out of range", n_obs);
-    iod_options o{1e-3, IOD_COST_PAPER, 0};
-    if (opt) o = *opt;
-    if (o.cost_mode != IOD_COST_PAPER && o.cost_mode != IOD_COST_CHI2)
-        return fail(IOD_EINVAL, "unknown cost_mode %d", o.cost_mode);
-    if (o.reserved != 0) return fail(IOD_EINVAL, "options.reserved must be 0");
-    for (int32_t k = 0; k < 2 * n_obs; ++k)
-        if (!std::isfinite(obs_angles[k])) return fail(IOD_EINVAL, "non-finite obs_angles[%d]", k);
-    std::vector<int64_t> ns(n_obs);
-    std::vector<double> tau(n_obs);
-    int rc = iod_schedule(obs_times, n_obs, o.h, ns.data(), tau.data());
+    HostProblem P;
+    int rc = make_problem(mu, chief_state, obs_times, obs_angles, n_obs, sigma, opt, P);
     if (rc != IOD_OK) return rc;
-
     iod_handle *h = new (std::nothrow) iod_handle;
     if (!h) return fail(IOD_ENOMEM, "host allocation");
-    hipError_t e = hipGetDevice(&h->device);
-    if (e != hipSuccess) {
-        delete h;
-        return hip_fail(e, "hipGetDevice");
-    }
-    h->mu = mu;
-    h->mu1 = 1.0 - mu;
-    h->h = o.h;
-    h->sigma = sigma;
-    h->w = 1.0 / (sigma * sigma);
-    h->K = n_obs;
-    h->mode = o.cost_mode;
-    std::memcpy(h->chief, chief_state, sizeof h->chief);
-    h->rc.assign(3 * (size_t)n_obs, 0.0);
-
-    std::vector<double> tab((size_t)n_obs * TAB_W, 0.0);
-    std::vector<int32_t> ns32(n_obs);
-    for (int32_t k = 0; k < n_obs; ++k) ns32[k] = (int32_t)ns[k];
-    for (int32_t k = 0; k < n_obs; ++k) {
-        double *row = &tab[(size_t)k * TAB_W];
-        row[TAB_NS] = (double)ns[k];
-        row[TAB_TAU] = tau[k];
-        row[TAB_SA] = std::sin(obs_angles[2 * k]);
-        row[TAB_CA] = std::cos(obs_angles[2 * k]);
-        row[TAB_SB] = std::sin(obs_angles[2 * k + 1]);
-        row[TAB_CB] = std::cos(obs_angles[2 * k + 1]);
-    }
-
-    // Chief ephemeris: propagate the chief with the particle propagator.
-    double *d_x = nullptr, *d_st = nullptr;
-    std::vector<double> st((size_t)n_obs * 6);
-    auto cleanup = [&](int code) {
-        if (d_x) (void)hipFree(d_x);
-        if (d_st) (void)hipFree(d_st);
-        if (code != IOD_OK) {
-            if (h->d_tab) (void)hipFree(h->d_tab);
-            if (h->d_ns) (void)hipFree(h->d_ns);
-            delete h;
-        }
+    h->P = std::move(P);
+    auto bail = [&](int code) {
+        iod_destroy(h);
         return code;
     };
-#define CREATE_TRY(expr)                                   \
-    do {                                                   \
-        hipError_t e_ = (expr);                            \
-        if (e_ != hipSuccess) return cleanup(hip_fail(e_, #expr)); \
-    } while (0)
-    CREATE_TRY(hipMalloc(&h->d_tab, tab.size() * sizeof(double)));
-    CREATE_TRY(hipMalloc(&h->d_ns, ns32.size() * sizeof(int32_t)));
-    CREATE_TRY(hipMemcpy(h->d_ns, ns32.data(), ns32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    CREATE_TRY(hipMalloc(&d_x, 6 * sizeof(double)));
-    CREATE_TRY(hipMalloc(&d_st, st.size() * sizeof(double)));
-    CREATE_TRY(hipMemcpy(h->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-    CREATE_TRY(hipMemcpy(d_x, chief_state, 6 * sizeof(double), hipMemcpyHostToDevice));
-    CREATE_TRY(launch_propagate(h->kargs(), d_x, 1, 1, d_st, nullptr));
-    CREATE_TRY(hipMemcpy(st.data(), d_st, st.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (int32_t k = 0; k < n_obs; ++k)
-        for (int d = 0; d < 3; ++d) {
-            h->rc[3 * (size_t)k + d] = st[6 * (size_t)k + d];
-            tab[(size_t)k * TAB_W + TAB_RC + d] = st[6 * (size_t)k + d];
-        }
-    CREATE_TRY(hipMemcpy(h->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
-#undef CREATE_TRY
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
+    const size_t K = (size_t)h->P.K;
+    if ((e = hipMalloc(&h->d_tab, K * TAB_W * sizeof(double))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc table"));
+    if ((e = hipMalloc(&h->d_ns, K * sizeof(int32_t))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc steps"));
+    if ((e = hipMemcpy(h->d_tab, h->P.tab.data(), K * TAB_W * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->d_ns, h->P.ns.data(), K * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy tables"));
+    // chief ephemeris, written into the device table
+    const ProbDesc D = desc_of(h->kargs(), h->P.chief, nullptr);
+    if ((e = launch_chief(D, nullptr, 1, nullptr)) != hipSuccess) return bail(hip_fail(e, "chief launch"));
+    std::vector<double> tab(K * TAB_W);
+    if ((e = hipMemcpy(tab.data(), h->d_tab, tab.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy chief"));
+    h->rc.resize(3 * K);
+    for (size_t k = 0; k < K; ++k)
+        for (int d = 0; d < 3; ++d) h->rc[3 * k + d] = tab[k * TAB_W + TAB_RC + d];
     *out = h;
-    return cleanup(IOD_OK);
+    return IOD_OK;
 }
 
 int iod_destroy(iod_handle *h)
@@ -285,23 +404,33 @@ int iod_destroy(iod_handle *h)
     if (hipSetDevice(h->device) == hipSuccess) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
-        if (h->d_tab) {
-            e = hipFree(h->d_tab);
-            if (e != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
-        }
-        if (h->d_ns) {
-            e = hipFree(h->d_ns);
-            if (e != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
-        }
+        if (h->d_tab && (e = hipFree(h->d_tab)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
+        if (h->d_ns && (e = hipFree(h->d_ns)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
     }
     delete h;
     return rc;
 }
 
+int iod_set_config(iod_handle *h, const iod_launch_config *cfg)
+{
+    if (!h) return fail(IOD_EINVAL, "null handle");
+    int rc = check_config(cfg);
+    if (rc != IOD_OK) return rc;
+    h->cfg = *cfg;
+    return IOD_OK;
+}
+
+int iod_get_config(const iod_handle *h, iod_launch_config *cfg)
+{
+    if (!h || !cfg) return fail(IOD_EINVAL, "null pointer");
+    *cfg = h->cfg;
+    return IOD_OK;
+}
+
 int32_t iod_num_obs(const iod_handle *h)
 {
     if (!h) return fail(IOD_EINVAL, "null handle");
-    return h->K;
+    return h->P.K;
 }
 
 int iod_chief_positions(const iod_handle *h, double *out)
@@ -337,14 +466,25 @@ int iod_eval_swarm(iod_handle *h, const double *x, int64_t ld, int64_t m, double
     int rc = check_handle(h);
     if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, cost);
     if (rc != IOD_OK || m == 0) return rc;
-    HIP_TRY(launch_eval(h->kargs(), x, ld, m, cost, (hipStream_t)stream));
+    const int bs = block_of(h->cfg);
+    ProbDesc D = desc_of(h->kargs(), h->P.chief, nullptr);
+    D.m = m;
+    D.nslots = ceil_div(m, bs);
+    D.block = bs;
+    SwarmArrays B;
+    std::memset(&B, 0, sizeof B);
+    B.x = const_cast<double *>(x);
+    B.cost = cost;
+    B.ld = ld;
+    B.nprob = 1;
+    HIP_TRY(launch_eval(D, B, bs, D.nslots, (hipStream_t)stream));
     return IOD_OK;
 }
 
 int64_t iod_swarm_work_len(int64_t m)
 {
-    if (m < 1) return fail(IOD_EINVAL, "m = %lld < 1", (long long)m);
-    return work_len(m);
+    if (m < 1 || m > MAX_M) return fail(IOD_EINVAL, "m = %lld out of range", (long long)m);
+    return 2 * ceil_div(m, 64) * REC + 2 * REC;
 }
 
 int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *stream)
@@ -354,7 +494,11 @@ int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *s
     if (rc == IOD_OK) rc = check_pso(p);
     if (rc != IOD_OK) return rc;
     s->iter = -1;
-    HIP_TRY(launch_swarm_init(h->kargs(), pso_args(p), swarm_args(s), (hipStream_t)stream));
+    s->block = block_of(h->cfg);
+    ProbDesc D;
+    SwarmArrays B;
+    single_view(h, s, p, D, B);
+    HIP_TRY(launch_swarm_init(D, B, s->block, D.nslots, (hipStream_t)stream));
     s->iter = 0;
     return IOD_OK;
 }
@@ -366,11 +510,11 @@ int iod_step(iod_handle *h, iod_swarm *s, const iod_pso_params *p, int64_t n_ite
     if (rc == IOD_OK) rc = check_pso(p);
     if (rc != IOD_OK) return rc;
     if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
-    const KArgs A = h->kargs();
-    const PsoArgs P = pso_args(p);
-    const SwarmArgs S = swarm_args(s);
-    for (int64_t j = 0; j < n_iter; ++j) {
-        HIP_TRY(launch_swarm_iter(A, P, S, s->iter + 1, (hipStream_t)stream));
+    ProbDesc D;
+    SwarmArrays B;
+    single_view(h, s, p, D, B);
+    for (int64_t j = 1; j <= n_iter; ++j) {
+        HIP_TRY(launch_swarm_iter(D, B, s->block, D.nslots, s->iter + 1, (hipStream_t)stream));
         s->iter += 1;
     }
     return IOD_OK;
@@ -382,12 +526,13 @@ int iod_swarm_best(iod_handle *h, iod_swarm *s, double best_state[6], double *be
     int rc = check_handle(h);
     if (rc == IOD_OK) rc = check_swarm(s, true);
     if (rc != IOD_OK) return rc;
-    const SwarmArgs S = swarm_args(s);
+    ProbDesc D;
+    SwarmArrays B;
+    single_view(h, s, nullptr, D, B);
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(launch_swarm_final(S, s->iter, st));
+    HIP_TRY(launch_swarm_final(D, B, s->iter, st));
     double rec[REC];
-    const double *d_rec = s->work + 2 * S.nslots * REC + (s->iter & 1) * REC;
-    HIP_TRY(hipMemcpyAsync(rec, d_rec, sizeof rec, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(rec, B.recs + (s->iter & 1) * REC, sizeof rec, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (best_state) std::memcpy(best_state, rec + 2, 6 * sizeof(double));
     if (best_cost) *best_cost = rec[0];
@@ -401,42 +546,402 @@ int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
     int rc = check_handle(h);
     if (rc == IOD_OK) rc = check_pso(p);
     if (rc != IOD_OK) return rc;
-    if (m < 1 || m > (int64_t)0x7fffffff * BS) return fail(IOD_EINVAL, "m out of range");
+    if (m < 1 || m > MAX_M) return fail(IOD_EINVAL, "m out of range");
     if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
-    const int64_t ld = (m + 63) / 64 * 64;
-    const int64_t wl = work_len(m);
+    const int64_t ld = round64(m);
+    const int64_t wl = iod_swarm_work_len(m);
     const size_t total = (size_t)(20 * ld + wl + (n_iter + 1));
-    double *buf = nullptr;
-    hipStream_t st = nullptr;
-    HIP_TRY(hipStreamCreate(&st));
-    hipError_t e = hipMalloc(&buf, total * sizeof(double));
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(st);
-        return hip_fail(e, "hipMalloc");
-    }
+    Stream st;
+    DevBuf buf;
+    HIP_TRY(hipStreamCreate(&st.s));
+    HIP_TRY(hipMalloc(&buf.p, total * sizeof(double)));
+    double *base = (double *)buf.p;
     iod_swarm s;
-    s.x = buf;
-    s.v = buf + 6 * ld;
-    s.p = buf + 12 * ld;
-    s.jp = buf + 18 * ld;
-    s.cost = buf + 19 * ld;
-    s.work = buf + 20 * ld;
-    s.hist = buf + 20 * ld + wl;
+    std::memset(&s, 0, sizeof s);
+    s.x = base;
+    s.v = base + 6 * ld;
+    s.p = base + 12 * ld;
+    s.jp = base + 18 * ld;
+    s.cost = base + 19 * ld;
+    s.work = base + 20 * ld;
+    s.hist = base + 20 * ld + wl;
     s.hist_len = n_iter + 1;
     s.ld = ld;
     s.m = m;
     s.iter = -1;
-    rc = iod_swarm_init(h, &s, p, st);
-    if (rc == IOD_OK) rc = iod_step(h, &s, p, n_iter, st);
-    if (rc == IOD_OK) rc = iod_swarm_best(h, &s, best_state, best_cost, nullptr, st);
+    rc = iod_swarm_init(h, &s, p, st.s);
+    if (rc == IOD_OK) {
+        ProbDesc D;
+        SwarmArrays B;
+        single_view(h, &s, p, D, B);
+        rc = run_iterations(st.s, h->cfg.graph != 0, 0, n_iter, [&](int64_t n) {
+            return launch_swarm_iter(D, B, s.block, D.nslots, n, st.s);
+        });
+        if (rc == IOD_OK) s.iter = n_iter;
+    }
+    if (rc == IOD_OK) rc = iod_swarm_best(h, &s, best_state, best_cost, nullptr, st.s);
     if (rc == IOD_OK && history) {
-        e = hipMemcpy(history, s.hist, (size_t)(n_iter + 1) * sizeof(double), hipMemcpyDeviceToHost);
+        hipError_t e = hipMemcpy(history, s.hist, (size_t)(n_iter + 1) * sizeof(double), hipMemcpyDeviceToHost);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy history");
     }
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(buf);
-    (void)hipStreamDestroy(st);
+    (void)hipStreamSynchronize(st.s);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+int iod_create_batch(int32_t n_problems, const double *mu, const double *chief_states,
+                     const int64_t *obs_offsets, const double *obs_times,
+                     const double *obs_angles, const double *sigma, const iod_options *opt,
+                     iod_batch **out)
+{
+    if (!out) return fail(IOD_EINVAL, "null out");
+    *out = nullptr;
+    if (n_problems < 1) return fail(IOD_EINVAL, "n_problems = %d < 1", n_problems);
+    if (!mu || !chief_states || !obs_offsets || !obs_times || !obs_angles || !sigma)
+        return fail(IOD_EINVAL, "null host pointer");
+    if (obs_offsets[0] != 0) return fail(IOD_EINVAL, "obs_offsets[0] must be 0");
+    iod_batch *b = new (std::nothrow) iod_batch;
+    if (!b) return fail(IOD_ENOMEM, "host allocation");
+    auto bail = [&](int code) {
+        iod_batch_destroy(b);
+        return code;
+    };
+    b->P = n_problems;
+    b->probs.resize(n_problems);
+    b->tab_off.resize(n_problems);
+    int64_t rows = 0;
+    for (int32_t p = 0; p < n_problems; ++p) {
+        const int64_t K = obs_offsets[p + 1] - obs_offsets[p];
+        if (K < 1 || K > IOD_MAX_OBS)
+            return bail(fail(IOD_EINVAL, "problem %d: %lld observations", p, (long long)K));
+        int rc = make_problem(mu[p], chief_states + 6 * (size_t)p, obs_times + obs_offsets[p],
+                              obs_angles + 2 * obs_offsets[p], (int32_t)K, sigma[p],
+                              opt ? opt + p : nullptr, b->probs[p]);
+        if (rc != IOD_OK) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "%s", g_err);
+            return bail(fail(rc, "problem %d: %s", p, msg));
+        }
+        b->tab_off[p] = rows;
+        rows += K;
+    }
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
+    std::vector<double> tab((size_t)rows * TAB_W);
+    std::vector<int32_t> ns((size_t)rows);
+    for (int32_t p = 0; p < n_problems; ++p) {
+        std::copy(b->probs[p].tab.begin(), b->probs[p].tab.end(), tab.begin() + b->tab_off[p] * TAB_W);
+        std::copy(b->probs[p].ns.begin(), b->probs[p].ns.end(), ns.begin() + b->tab_off[p]);
+    }
+    if ((e = hipMalloc(&b->d_tab, tab.size() * sizeof(double))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc table"));
+    if ((e = hipMalloc(&b->d_ns, ns.size() * sizeof(int32_t))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc steps"));
+    if ((e = hipMemcpy(b->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->d_ns, ns.data(), ns.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy tables"));
+    // chief ephemerides of all problems in one launch
+    std::vector<ProbDesc> descs(n_problems);
+    for (int32_t p = 0; p < n_problems; ++p) descs[p] = desc_of(b->kargs(p), b->probs[p].chief, nullptr);
+    DevBuf d_desc;
+    if ((e = hipMalloc(&d_desc.p, descs.size() * sizeof(ProbDesc))) != hipSuccess)
+        return bail(hip_fail(e, "hipMalloc descriptors"));
+    if ((e = hipMemcpy(d_desc.p, descs.data(), descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy descriptors"));
+    if ((e = launch_chief(descs[0], (const ProbDesc *)d_desc.p, n_problems, nullptr)) != hipSuccess)
+        return bail(hip_fail(e, "chief launch"));
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(hip_fail(e, "chief ephemerides"));
+    *out = b;
+    return IOD_OK;
+}
+
+int iod_batch_destroy(iod_batch *b)
+{
+    if (!b) return IOD_OK;
+    int rc = IOD_OK;
+    if (hipSetDevice(b->device) == hipSuccess) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+        if (b->d_tab && (e = hipFree(b->d_tab)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
+        if (b->d_ns && (e = hipFree(b->d_ns)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
+    }
+    delete b;
+    return rc;
+}
+
+int32_t iod_batch_size(const iod_batch *b)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    return b->P;
+}
+
+int64_t iod_batch_steps(const iod_batch *b, int32_t p)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    if (p < 0 || p >= b->P) return fail(IOD_EINVAL, "problem %d out of range", p);
+    return b->probs[p].steps;
+}
+
+int iod_batch_set_config(iod_batch *b, const iod_launch_config *cfg)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    int rc = check_config(cfg);
+    if (rc != IOD_OK) return rc;
+    b->cfg = *cfg;
+    return IOD_OK;
+}
+
+int iod_batch_get_config(const iod_batch *b, iod_launch_config *cfg)
+{
+    if (!b || !cfg) return fail(IOD_EINVAL, "null pointer");
+    *cfg = b->cfg;
+    return IOD_OK;
+}
+
+int64_t iod_batch_offsets(const iod_batch *b, const int64_t *m, int64_t *off)
+{
+    if (!b || !m || !off) return fail(IOD_EINVAL, "null pointer");
+    int64_t o = 0;
+    for (int32_t p = 0; p < b->P; ++p) {
+        if (m[p] < 0 || m[p] > MAX_M) return fail(IOD_EINVAL, "problem %d: m out of range", p);
+        off[p] = o;
+        o += round64(m[p]);
+    }
+    off[b->P] = o;
+    return o;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device-side layout of one batched launch: descriptors and work list.
+struct BatchLayout {
+    std::vector<ProbDesc> descs;
+    std::vector<int32_t> work;  // [grid][2]
+    int64_t ld = 0, total_slots = 0, grid = 0;
+};
+
+int batch_layout(const iod_batch *b, const iod_pso_params *params, const int64_t *m, int bs,
+                 int order, BatchLayout &L)
+{
+    std::vector<int64_t> off(b->P + 1);
+    int64_t ld = iod_batch_offsets(b, m, off.data());
+    if (ld < 0) return (int)ld;
+    L.ld = ld;
+    L.descs.resize(b->P);
+    int64_t slots = 0;
+    for (int32_t p = 0; p < b->P; ++p) {
+        ProbDesc &D = L.descs[p];
+        D = desc_of(b->kargs(p), b->probs[p].chief, params ? params + p : nullptr);
+        D.m = m[p];
+        D.off = off[p];
+        D.slot_off = slots;
+        D.nslots = ceil_div(m[p], bs);
+        D.block = bs;
+        slots += D.nslots;
+    }
+    L.total_slots = slots;
+    std::vector<int32_t> pord(b->P);
+    std::iota(pord.begin(), pord.end(), 0);
+    if (order == IOD_ORDER_LONGEST_FIRST)
+        std::stable_sort(pord.begin(), pord.end(), [&](int32_t a, int32_t c) {
+            return b->probs[a].steps > b->probs[c].steps;
+        });
+    L.work.clear();
+    for (int32_t p : pord)
+        for (int64_t t = 0; t < L.descs[p].nslots; ++t) {
+            L.work.push_back(p);
+            L.work.push_back((int32_t)t);
+        }
+    L.grid = (int64_t)L.work.size() / 2;
+    if (L.grid > 0x7fffffff) return fail(IOD_EINVAL, "batch too large for one launch");
+    return IOD_OK;
+}
+
+// Allocates and runs one batched solve; optional timing of the iterations.
+int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
+              const iod_launch_config &cfg, double *best_states, double *best_costs,
+              double *history, double *iter_ms)
+{
+    const int bs = block_of(cfg);
+    BatchLayout L;
+    int rc = batch_layout(b, params, m, bs, cfg.order, L);
+    if (rc != IOD_OK) return rc;
+    const int64_t P = b->P, ld = L.ld;
+    const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1));
+    Stream st;
+    DevBuf dbuf, ddesc, dwork;
+    HIP_TRY(hipStreamCreate(&st.s));
+    HIP_TRY(hipMalloc(&dbuf.p, nd * sizeof(double)));
+    double *base = (double *)dbuf.p;
+    double *hist = base + 20 * ld + 2 * L.total_slots * REC + 2 * P * REC;
+    for (int64_t p = 0; p < P; ++p) {
+        L.descs[p].hist = hist + p * (n_iter + 1);
+        L.descs[p].hist_len = n_iter + 1;
+    }
+    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st.s));
+    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st.s));
+    SwarmArrays B;
+    B.desc = (const ProbDesc *)ddesc.p;
+    B.work = (const int32_t *)dwork.p;
+    B.x = base;
+    B.v = base + 6 * ld;
+    B.p = base + 12 * ld;
+    B.jp = base + 18 * ld;
+    B.cost = base + 19 * ld;
+    B.slots = base + 20 * ld;
+    B.recs = B.slots + 2 * L.total_slots * REC;
+    B.ld = ld;
+    B.total_slots = L.total_slots;
+    B.nprob = P;
+    const ProbDesc &d0 = L.descs[0];
+    HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st.s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (iter_ms) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        // the first iteration reuses the initial evaluation: run it untimed
+        HIP_TRY(launch_swarm_iter(d0, B, bs, L.grid, 1, st.s));
+        HIP_TRY(hipEventRecord(e0, st.s));
+    }
+    const int64_t n0 = iter_ms ? 1 : 0;
+    rc = run_iterations(st.s, cfg.graph != 0, n0, n_iter - n0, [&](int64_t n) {
+        return launch_swarm_iter(d0, B, bs, L.grid, n, st.s);
+    });
+    if (rc == IOD_OK && iter_ms) {
+        hipError_t e = hipEventRecord(e1, st.s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = hip_fail(e, "iteration timing");
+        *iter_ms = n_iter > n0 ? ms / (double)(n_iter - n0) : 0.0;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc == IOD_OK) {
+        hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
+        if (e != hipSuccess) rc = hip_fail(e, "final launch");
+    }
+    if (rc == IOD_OK && (best_states || best_costs)) {
+        std::vector<double> recs((size_t)P * REC);
+        hipError_t e = hipMemcpyAsync(recs.data(), B.recs + (n_iter & 1) * P * REC, recs.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, st.s);
+        if (e == hipSuccess) e = hipStreamSynchronize(st.s);
+        if (e != hipSuccess) return hip_fail(e, "read-back");
+        for (int64_t p = 0; p < P; ++p) {
+            if (best_states) std::memcpy(best_states + 6 * p, &recs[p * REC + 2], 6 * sizeof(double));
+            if (best_costs) best_costs[p] = recs[p * REC];
+        }
+    }
+    if (rc == IOD_OK && history) {
+        hipError_t e = hipMemcpyAsync(history, hist, (size_t)P * (n_iter + 1) * sizeof(double),
+                                      hipMemcpyDeviceToHost, st.s);
+        if (e == hipSuccess) e = hipStreamSynchronize(st.s);
+        if (e != hipSuccess) return hip_fail(e, "history read-back");
+    }
+    hipError_t e = hipStreamSynchronize(st.s);
+    if (rc == IOD_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    return rc;
+}
+
+int check_batch_swarm_args(const iod_batch *b, const iod_pso_params *params, const int64_t *m)
+{
+    if (!params || !m) return fail(IOD_EINVAL, "null host pointer");
+    for (int32_t p = 0; p < b->P; ++p) {
+        if (m[p] < 1 || m[p] > MAX_M) return fail(IOD_EINVAL, "problem %d: m out of range", p);
+        int rc = check_pso(params + p);
+        if (rc != IOD_OK) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(rc, "problem %d: %s", p, msg);
+        }
+    }
+    return IOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                   void *stream)
+{
+    int rc = check_batch(b);
+    if (rc != IOD_OK) return rc;
+    if (!m) return fail(IOD_EINVAL, "null m");
+    const int bs = block_of(b->cfg);
+    BatchLayout L;
+    rc = batch_layout(b, nullptr, m, bs, b->cfg.order, L);
+    if (rc != IOD_OK) return rc;
+    if (ld < L.ld) return fail(IOD_EINVAL, "ld = %lld < %lld", (long long)ld, (long long)L.ld);
+    if (L.grid == 0) return IOD_OK;
+    if (!x || !cost) return fail(IOD_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf ddesc, dwork;
+    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SwarmArrays B;
+    std::memset(&B, 0, sizeof B);
+    B.desc = (const ProbDesc *)ddesc.p;
+    B.work = (const int32_t *)dwork.p;
+    B.x = const_cast<double *>(x);
+    B.cost = cost;
+    B.ld = ld;
+    B.nprob = b->P;
+    B.total_slots = L.total_slots;
+    HIP_TRY(launch_eval(L.descs[0], B, bs, L.grid, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IOD_OK;
+}
+
+int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
+                    double *best_states, double *best_costs, double *history)
+{
+    int rc = check_batch(b);
+    if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
+    if (rc != IOD_OK) return rc;
+    if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    return batch_run(b, params, m, n_iter, b->cfg, best_states, best_costs, history, nullptr);
+}
+
+int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                       int64_t trial_iters, iod_launch_config *chosen, double *ms_per_iter,
+                       int32_t *n_candidates)
+{
+    int rc = check_batch(b);
+    if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
+    if (rc != IOD_OK) return rc;
+    if (trial_iters < 2) return fail(IOD_EINVAL, "trial_iters must be >= 2");
+    const int blocks[3] = {64, 128, 256};
+    iod_launch_config best{256, IOD_ORDER_LONGEST_FIRST, 1, 0};
+    double best_ms = INFINITY;
+    int32_t c = 0;
+    for (int bi = 0; bi < 3; ++bi)
+        for (int order = 0; order < 2; ++order)
+            for (int graph = 0; graph < 2; ++graph) {
+                iod_launch_config cfg{blocks[bi], order, graph, 0};
+                double ms = 0;
+                rc = batch_run(b, params, m, trial_iters, cfg, nullptr, nullptr, nullptr, &ms);
+                if (rc != IOD_OK) return rc;
+                if (ms_per_iter) ms_per_iter[c] = ms;
+                ++c;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cfg;
+                }
+            }
+    if (n_candidates) *n_candidates = c;
+    b->cfg = best;
+    if (chosen) *chosen = best;
+    return IOD_OK;
 }
 
 }  // extern "C"

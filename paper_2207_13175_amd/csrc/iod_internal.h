@@ -19,12 +19,10 @@ constexpr int TAB_NS = 0, TAB_TAU = 1, TAB_RC = 2, TAB_SA = 5, TAB_CA = 6, TAB_S
 // Rows staged in LDS at a time by every workgroup.
 constexpr int OBS_CHUNK = 64;
 
-// Threads per workgroup of every swarm kernel (4 wave64).
-constexpr int BS = 256;
-
-// Global-best record: [key, index, state[6]].
+// Global-best record and argmin slot: [key, index, state[6]].
 constexpr int REC = 8;
 
+// Dynamics, observation table and cost of one problem.
 struct KArgs {
     const double *tab;  // device [K][TAB_W]
     const int32_t *ns;  // device [K] whole steps before each observation
@@ -36,33 +34,46 @@ struct KArgs {
     double w;           // 1 / sigma^2
 };
 
-struct PsoArgs {
-    double omega, eta1, eta2;
-    uint64_t seed, problem;
-    double lo[6], hi[6];
-};
-
-struct SwarmArgs {
-    double *x, *v, *p, *jp, *cost;
-    double *work;       // slots [2][nslots][REC], then records [2][REC]
-    double *hist;
+// One problem of a swarm launch (a single problem or one member of a batch).
+struct ProbDesc {
+    KArgs k;
+    double omega, eta1, eta2;   // Algorithm 1 weights
+    double lo[6], hi[6];        // initialisation box
+    double chief[6];            // chief state at t = 0
+    uint64_t seed, problem;     // Philox key word 0, counter word 2
+    double *hist;               // device [hist_len] global-best costs, or null
     int64_t hist_len;
-    int64_t ld, m, nslots;
+    int64_t m;                  // particles
+    int64_t off;                // first particle in the swarm arrays
+    int64_t slot_off;           // first argmin slot
+    int64_t nslots;             // ceil(m / block)
+    int32_t block;              // threads per workgroup of the swarm kernels
+    int32_t pad;
 };
 
-inline int64_t num_slots(int64_t m) { return (m + BS - 1) / BS; }
-inline int64_t work_len(int64_t m) { return 2 * num_slots(m) * REC + 2 * REC; }
+// Swarm storage of one launch. desc/work are null for a single problem.
+struct SwarmArrays {
+    const ProbDesc *desc;       // device [nprob]
+    const int32_t *work;        // device [grid][2] = (problem, tile)
+    double *x, *v, *p, *jp, *cost;  // [6][ld] / [ld] structure of arrays
+    double *slots;              // [2][total_slots][REC]
+    double *recs;               // [2][nprob][REC]
+    int64_t ld, total_slots, nprob;
+};
 
 hipError_t launch_propagate(const KArgs &A, const double *x, int64_t ld, int64_t m,
                             double *states, hipStream_t st);
 hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m,
                           double *angles, hipStream_t st);
-hipError_t launch_eval(const KArgs &A, const double *x, int64_t ld, int64_t m, double *cost,
+// descs == null: the single problem d0.
+hipError_t launch_chief(const ProbDesc &d0, const ProbDesc *descs, int64_t nprob, hipStream_t st);
+// bs in {64, 128, 256}; grid = workgroups (nslots for a single problem).
+hipError_t launch_eval(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                        hipStream_t st);
-hipError_t launch_swarm_init(const KArgs &A, const PsoArgs &P, const SwarmArgs &S,
+hipError_t launch_swarm_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                              hipStream_t st);
-hipError_t launch_swarm_iter(const KArgs &A, const PsoArgs &P, const SwarmArgs &S, int64_t n,
-                             hipStream_t st);
-hipError_t launch_swarm_final(const SwarmArgs &S, int64_t n, hipStream_t st);
+hipError_t launch_swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                             int64_t n, hipStream_t st);
+hipError_t launch_swarm_final(const ProbDesc &d0, const SwarmArrays &B, int64_t n, hipStream_t st);
 
 }  // namespace iodk

@@ -289,7 +289,7 @@ __device__ __forceinline__ bool lex_less(double ka, double ia, double kb, double
     return ka < kb || (ka == kb && ia < ib);
 }
 
-// Block-wide argmin; every thread returns the minimum. red: LDS [2 * BS/64].
+// Block-wide argmin; every thread returns the minimum. red: LDS [2 * waves].
 __device__ __forceinline__ void block_argmin(double &key, double &idx, double *red)
 {
 #pragma unroll
@@ -317,8 +317,9 @@ __device__ __forceinline__ void block_argmin(double &key, double &idx, double *r
     __syncthreads();
 }
 
-// Workgroup argmin of (key(jp), i) over its valid particles, written with the
-// winner's state to slot `slot` as [key, index, state[6]].
+// Workgroup argmin of (key(jp), i) over its valid particles (i counted within
+// the problem), written with the winner's state to `slot` as
+// [key, index, state[6]].
 __device__ __forceinline__ void write_slot(double jp, int64_t i, bool valid, const double st[6],
                                            double *slot, double *red, double *wst)
 {
@@ -330,12 +331,15 @@ __device__ __forceinline__ void write_slot(double jp, int64_t i, bool valid, con
         for (int d = 0; d < 6; ++d) wst[d] = st[d];
     }
     __syncthreads();
-    if (threadIdx.x < REC) slot[threadIdx.x] = threadIdx.x == 0 ? key : threadIdx.x == 1 ? idx : wst[threadIdx.x - 2];
+    if (threadIdx.x < REC)
+        slot[threadIdx.x] = threadIdx.x == 0 ? key : threadIdx.x == 1 ? idx : wst[threadIdx.x - 2];
 }
 
-// Global best G_{n-1} = merge(record G_{n-2}, slots of launch n-1): the slot
+// Global best of one problem: merge(record, the problem's slots). The slot
 // minimum replaces the record if the record is empty (index < 0) or the slot
-// cost is strictly lower. Every workgroup computes the same result.
+// cost is strictly lower. Slot s holds the minimum of particles
+// [s * blockDim, (s + 1) * blockDim). Every workgroup of the problem computes
+// the same result.
 __device__ __forceinline__ void reduce_global(const double *slots, int64_t nslots,
                                               const double *prev, double g[6], double &gkey,
                                               double &gidx, double *red)
@@ -351,7 +355,7 @@ __device__ __forceinline__ void reduce_global(const double *slots, int64_t nslot
     block_argmin(key, idx, red);
     const double pk = prev[0], pi = prev[1];
     if (pi < 0.0 || key < pk) {
-        const int64_t s = (int64_t)idx / BS;
+        const int64_t s = (int64_t)idx / blockDim.x;
         gkey = key;
         gidx = idx;
 #pragma unroll
@@ -364,8 +368,19 @@ __device__ __forceinline__ void reduce_global(const double *slots, int64_t nslot
     }
 }
 
+__device__ __forceinline__ void write_record(double *rec, const double g[6], double gkey,
+                                             double gidx)
+{
+    if (threadIdx.x < REC)
+        rec[threadIdx.x] = threadIdx.x == 0 ? gkey : threadIdx.x == 1 ? gidx : g[threadIdx.x - 2];
+}
+
 // ---------------------------------------------------------------------------
-// Kernels.
+// Kernels. Swarm kernels serve one problem (SINGLE: the descriptor is a
+// kernel argument, workgroup b is tile b) or a batch (the descriptors live in
+// device memory and a work list maps workgroup b to (problem, tile), ordered
+// longest problem first so the dispatcher's greedy placement balances the
+// uneven work).
 // ---------------------------------------------------------------------------
 
 struct StoreStates {
@@ -408,19 +423,47 @@ struct StoreAngles {
     }
 };
 
+// Chief positions written into the observation table of each problem.
+struct StoreChief {
+    double *tab;
+    int32_t k;
+    __device__ __forceinline__ void operator()(const double *, const double S[6])
+    {
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) tab[(int64_t)k * TAB_W + TAB_RC + d] = S[d];
+        }
+        ++k;
+    }
+};
+
 __device__ __forceinline__ void load_state(const double *x, int64_t ld, int64_t j, double X[6])
 {
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = x[d * ld + j];
 }
 
-__global__ __launch_bounds__(BS) void k_propagate(KArgs A, const double *__restrict__ x,
-                                                  int64_t ld, int64_t m,
-                                                  double *__restrict__ states)
+template <bool SINGLE>
+__device__ __forceinline__ const ProbDesc &locate(const ProbDesc &d0, const SwarmArrays &B,
+                                                  int64_t &p, int64_t &tile)
+{
+    if (SINGLE) {
+        p = 0;
+        tile = blockIdx.x;
+        return d0;
+    }
+    p = B.work[2 * (int64_t)blockIdx.x];
+    tile = B.work[2 * (int64_t)blockIdx.x + 1];
+    return B.desc[p];
+}
+
+__global__ __launch_bounds__(256) void k_propagate(KArgs A, const double *__restrict__ x,
+                                                   int64_t ld, int64_t m,
+                                                   double *__restrict__ states)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < m;
     double X[6];
     load_state(x, ld, valid ? i : m - 1, X);
@@ -428,13 +471,13 @@ __global__ __launch_bounds__(BS) void k_propagate(KArgs A, const double *__restr
     walk(A, X, lds, lds_ns, obs);
 }
 
-__global__ __launch_bounds__(BS) void k_predict(KArgs A, const double *__restrict__ x,
-                                                int64_t ld, int64_t m,
-                                                double *__restrict__ angles)
+__global__ __launch_bounds__(256) void k_predict(KArgs A, const double *__restrict__ x,
+                                                 int64_t ld, int64_t m,
+                                                 double *__restrict__ angles)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < m;
     double X[6];
     load_state(x, ld, valid ? i : m - 1, X);
@@ -442,185 +485,251 @@ __global__ __launch_bounds__(BS) void k_predict(KArgs A, const double *__restric
     walk(A, X, lds, lds_ns, obs);
 }
 
-__global__ __launch_bounds__(BS) void k_eval(KArgs A, const double *__restrict__ x, int64_t ld,
-                                             int64_t m, double *__restrict__ cost)
+// One workgroup per problem; the chief is propagated with the particle
+// integrator and schedule (its positions do not enter the propagation).
+template <bool SINGLE>
+__global__ __launch_bounds__(64) void k_chief(ProbDesc d0, const ProbDesc *__restrict__ descs)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-    const bool valid = i < m;
+    const ProbDesc &D = SINGLE ? d0 : descs[blockIdx.x];
     double X[6];
-    load_state(x, ld, valid ? i : m - 1, X);
-    const double J = eval_cost(A, X, lds, lds_ns);
-    if (valid) cost[i] = J;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = D.chief[d];
+    StoreChief obs{const_cast<double *>(D.k.tab), 0};
+    walk(D.k, X, lds, lds_ns, obs);
+}
+
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_eval(ProbDesc d0, SwarmArrays B)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    double X[6];
+    load_state(B.x, B.ld, D.off + (valid ? i : D.m - 1), X);
+    const double J = eval_cost(D.k, X, lds, lds_ns);
+    if (valid) B.cost[D.off + i] = J;
 }
 
 // Algorithm 1 initialisation.
-__global__ __launch_bounds__(BS) void k_swarm_init(KArgs A, PsoArgs P, SwarmArgs S)
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
     __shared__ double red[2 * (BS / 64)];
     __shared__ double wst[6];
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-    const bool valid = i < S.m;
-    const int64_t j = valid ? i : S.m - 1;
-    uint64_t u[8] = {0, (uint64_t)j, P.problem, 0, 1, (uint64_t)j, P.problem, 0};
-    philox4x64_10(u, P.seed, 0);
-    philox4x64_10(u + 4, P.seed, 0);
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t j = valid ? i : D.m - 1;
+    uint64_t u[8] = {0, (uint64_t)j, D.problem, 0, 1, (uint64_t)j, D.problem, 0};
+    philox4x64_10(u, D.seed, 0);
+    philox4x64_10(u + 4, D.seed, 0);
     double X[6];
 #pragma unroll
-    for (int d = 0; d < 6; ++d) X[d] = P.lo[d] + (P.hi[d] - P.lo[d]) * u01(u[d]);
-    const double J = eval_cost(A, X, lds, lds_ns);
+    for (int d = 0; d < 6; ++d) X[d] = D.lo[d] + (D.hi[d] - D.lo[d]) * u01(u[d]);
+    const double J = eval_cost(D.k, X, lds, lds_ns);
+    const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
-            S.x[d * S.ld + i] = X[d];
-            S.v[d * S.ld + i] = 0.0;
-            S.p[d * S.ld + i] = X[d];
+            B.x[d * ld + g] = X[d];
+            B.v[d * ld + g] = 0.0;
+            B.p[d * ld + g] = X[d];
         }
-        S.jp[i] = J;
-        S.cost[i] = J;
+        B.jp[g] = J;
+        B.cost[g] = J;
     }
-    double *slots0 = S.work;  // parity 0
-    write_slot(J, i, valid, X, slots0 + (int64_t)blockIdx.x * REC, red, wst);
-    if (blockIdx.x == 0 && threadIdx.x < REC) {
-        // record parity 1 = "before initialisation": empty
-        double *rec1 = S.work + 2 * S.nslots * REC + REC;
-        rec1[threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
-    }
+    // slots of parity 0; record of parity 1 = "before initialisation" (empty)
+    write_slot(J, i, valid, X, B.slots + (D.slot_off + tile) * REC, red, wst);
+    if (tile == 0 && threadIdx.x < REC)
+        B.recs[(B.nprob + p) * REC + threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
 }
 
 // Algorithm 1, iteration n >= 1.
-__global__ __launch_bounds__(BS) void k_swarm_iter(KArgs A, PsoArgs P, SwarmArgs S, int64_t n)
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, int64_t n)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
     __shared__ double red[2 * (BS / 64)];
     __shared__ double wst[6];
-    double *slots = S.work;
-    double *recs = S.work + 2 * S.nslots * REC;
-    const double *slots_prev = slots + ((n - 1) & 1) * S.nslots * REC;
-    double *slots_cur = slots + (n & 1) * S.nslots * REC;
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const double *slots_prev = B.slots + (((n - 1) & 1) * B.total_slots + D.slot_off) * REC;
+    double *slot_cur = B.slots + ((n & 1) * B.total_slots + D.slot_off + tile) * REC;
 
     // (a) global best of the previous iteration
     double g[6], gkey, gidx;
-    reduce_global(slots_prev, S.nslots, recs + (n & 1) * REC, g, gkey, gidx, red);
-    if (blockIdx.x == 0) {
-        double *rec = recs + ((n - 1) & 1) * REC;
-        if (threadIdx.x < REC)
-            rec[threadIdx.x] = threadIdx.x == 0 ? gkey : threadIdx.x == 1 ? gidx : g[threadIdx.x - 2];
-        if (threadIdx.x == 0 && S.hist && n - 1 < S.hist_len) S.hist[n - 1] = gkey;
+    reduce_global(slots_prev, D.nslots, B.recs + ((n & 1) * B.nprob + p) * REC, g, gkey, gidx,
+                  red);
+    if (tile == 0) {
+        write_record(B.recs + (((n - 1) & 1) * B.nprob + p) * REC, g, gkey, gidx);
+        if (threadIdx.x == 0 && D.hist && n - 1 < D.hist_len) D.hist[n - 1] = gkey;
     }
 
     // (b) evaluate, personal best, velocity and position
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-    const bool valid = i < S.m;
-    const int64_t j = valid ? i : S.m - 1;
-    const int64_t ld = S.ld;
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t j = valid ? i : D.m - 1;
+    const int64_t ld = B.ld, gj = D.off + j, gi = D.off + i;
     double X[6], V[6], Pb[6];
-    load_state(S.x, ld, j, X);
-    load_state(S.v, ld, j, V);
-    load_state(S.p, ld, j, Pb);
-    double jp = S.jp[j];
+    load_state(B.x, ld, gj, X);
+    load_state(B.v, ld, gj, V);
+    load_state(B.p, ld, gj, Pb);
+    double jp = B.jp[gj];
     double J;
     if (n >= 2)
-        J = eval_cost(A, X, lds, lds_ns);
+        J = eval_cost(D.k, X, lds, lds_ns);
     else
-        J = S.cost[j];
+        J = B.cost[gj];
     const bool better = cost_key(J) < cost_key(jp);
     if (better) {
         jp = J;
 #pragma unroll
         for (int d = 0; d < 6; ++d) Pb[d] = X[d];
     }
-    uint64_t c[4] = {(uint64_t)n, (uint64_t)j, P.problem, 1};
-    philox4x64_10(c, P.seed, 0);
-    const double a1 = P.eta1 * u01(c[0]);
-    const double a2 = P.eta2 * u01(c[1]);
+    uint64_t c[4] = {(uint64_t)n, (uint64_t)j, D.problem, 1};
+    philox4x64_10(c, D.seed, 0);
+    const double a1 = D.eta1 * u01(c[0]);
+    const double a2 = D.eta2 * u01(c[1]);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-        const double vn = P.omega * V[d] + a1 * (Pb[d] - X[d]) + a2 * (g[d] - X[d]);
+        const double vn = D.omega * V[d] + a1 * (Pb[d] - X[d]) + a2 * (g[d] - X[d]);
         V[d] = vn;
         X[d] = X[d] + vn;
     }
     if (valid) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
-            S.x[d * ld + i] = X[d];
-            S.v[d * ld + i] = V[d];
+            B.x[d * ld + gi] = X[d];
+            B.v[d * ld + gi] = V[d];
         }
-        if (n >= 2) S.cost[i] = J;
+        if (n >= 2) B.cost[gi] = J;
         if (better) {
 #pragma unroll
-            for (int d = 0; d < 6; ++d) S.p[d * ld + i] = Pb[d];
-            S.jp[i] = jp;
+            for (int d = 0; d < 6; ++d) B.p[d * ld + gi] = Pb[d];
+            B.jp[gi] = jp;
         }
     }
 
     // (c) this workgroup's best personal best, for the next launch
-    write_slot(jp, i, valid, Pb, slots_cur + (int64_t)blockIdx.x * REC, red, wst);
+    write_slot(jp, i, valid, Pb, slot_cur, red, wst);
 }
 
-// Global best after iteration n: G_n = merge(G_{n-1}, slots of launch n).
-__global__ __launch_bounds__(BS) void k_swarm_final(SwarmArgs S, int64_t n)
+// Global best after iteration n, one workgroup per problem:
+// G_n = merge(G_{n-1}, slots of launch n).
+template <bool SINGLE>
+__global__ __launch_bounds__(256) void k_swarm_final(ProbDesc d0, SwarmArrays B, int64_t n)
 {
-    __shared__ double red[2 * (BS / 64)];
-    double *slots = S.work;
-    double *recs = S.work + 2 * S.nslots * REC;
+    __shared__ double red[2 * (256 / 64)];
+    const int64_t p = SINGLE ? 0 : blockIdx.x;
+    const ProbDesc &D = SINGLE ? d0 : B.desc[p];
     double g[6], gkey, gidx;
-    reduce_global(slots + (n & 1) * S.nslots * REC, S.nslots, recs + ((n - 1) & 1) * REC, g,
-                  gkey, gidx, red);
-    double *rec = recs + (n & 1) * REC;
-    if (threadIdx.x < REC)
-        rec[threadIdx.x] = threadIdx.x == 0 ? gkey : threadIdx.x == 1 ? gidx : g[threadIdx.x - 2];
-    if (threadIdx.x == 0 && S.hist && n < S.hist_len) S.hist[n] = gkey;
+    // slot geometry is that of the swarm kernels (D.block threads per slot)
+    double key = INFINITY, idx = INFINITY;
+    const double *slots = B.slots + ((n & 1) * B.total_slots + D.slot_off) * REC;
+    for (int64_t s = threadIdx.x; s < D.nslots; s += blockDim.x) {
+        const double k = slots[s * REC], i = slots[s * REC + 1];
+        if (lex_less(k, i, key, idx)) {
+            key = k;
+            idx = i;
+        }
+    }
+    block_argmin(key, idx, red);
+    const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
+    if (prev[1] < 0.0 || key < prev[0]) {
+        const int64_t s = (int64_t)idx / D.block;
+        gkey = key;
+        gidx = idx;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = slots[s * REC + 2 + d];
+    } else {
+        gkey = prev[0];
+        gidx = prev[1];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = prev[2 + d];
+    }
+    write_record(B.recs + ((n & 1) * B.nprob + p) * REC, g, gkey, gidx);
+    if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = gkey;
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 
-static inline unsigned grid_for(int64_t m) { return (unsigned)((m + BS - 1) / BS); }
+static inline unsigned grid_for(int64_t m, int bs) { return (unsigned)((m + bs - 1) / bs); }
 
 hipError_t launch_propagate(const KArgs &A, const double *x, int64_t ld, int64_t m,
                             double *states, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_propagate, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, states);
+    hipLaunchKernelGGL(k_propagate, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, states);
     return hipGetLastError();
 }
 
 hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m,
                           double *angles, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_predict, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, angles);
+    hipLaunchKernelGGL(k_predict, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, angles);
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const KArgs &A, const double *x, int64_t ld, int64_t m, double *cost,
+hipError_t launch_chief(const ProbDesc &d0, const ProbDesc *descs, int64_t nprob, hipStream_t st)
+{
+    if (descs)
+        hipLaunchKernelGGL(k_chief<false>, dim3((unsigned)nprob), dim3(64), 0, st, d0, descs);
+    else
+        hipLaunchKernelGGL(k_chief<true>, dim3(1), dim3(64), 0, st, d0, descs);
+    return hipGetLastError();
+}
+
+#define IOD_DISPATCH_BS(BSV, ...)                                  \
+    switch (BSV) {                                                 \
+    case 64: { constexpr int BS_ = 64; __VA_ARGS__; break; }       \
+    case 128: { constexpr int BS_ = 128; __VA_ARGS__; break; }     \
+    case 256: { constexpr int BS_ = 256; __VA_ARGS__; break; }     \
+    default: return hipErrorInvalidValue;                          \
+    }
+
+hipError_t launch_eval(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_eval, dim3(grid_for(m)), dim3(BS), 0, st, A, x, ld, m, cost);
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_eval<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B);
+                        else hipLaunchKernelGGL((k_eval<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
     return hipGetLastError();
 }
 
-hipError_t launch_swarm_init(const KArgs &A, const PsoArgs &P, const SwarmArgs &S,
+hipError_t launch_swarm_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_swarm_init, dim3(grid_for(S.m)), dim3(BS), 0, st, A, P, S);
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_swarm_init<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B);
+                        else hipLaunchKernelGGL((k_swarm_init<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
     return hipGetLastError();
 }
 
-hipError_t launch_swarm_iter(const KArgs &A, const PsoArgs &P, const SwarmArgs &S, int64_t n,
-                             hipStream_t st)
+hipError_t launch_swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                             int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_swarm_iter, dim3(grid_for(S.m)), dim3(BS), 0, st, A, P, S, n);
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_swarm_iter<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n);
+                        else hipLaunchKernelGGL((k_swarm_iter<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
     return hipGetLastError();
 }
 
-hipError_t launch_swarm_final(const SwarmArgs &S, int64_t n, hipStream_t st)
+hipError_t launch_swarm_final(const ProbDesc &d0, const SwarmArrays &B, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_swarm_final, dim3(1), dim3(BS), 0, st, S, n);
+    if (B.desc)
+        hipLaunchKernelGGL(k_swarm_final<false>, dim3((unsigned)B.nprob), dim3(256), 0, st, d0, B, n);
+    else
+        hipLaunchKernelGGL(k_swarm_final<true>, dim3(1), dim3(256), 0, st, d0, B, n);
     return hipGetLastError();
 }
 

@@ -113,3 +113,75 @@ def random_swarm(seed: int, m: int, lo: np.ndarray, hi: np.ndarray) -> np.ndarra
     """[m, 6] particle states uniform in the box (test inputs, numpy PCG64)."""
     rng = np.random.default_rng([seed, 3])
     return lo + (hi - lo) * rng.random((m, 6))
+
+
+# Collinear libration points of the Earth-Moon system for MU_EARTH_MOON
+# (published values, used only as centres for drawing chief states).
+L1_X = 0.8369151288
+L2_X = 1.1556821631
+
+
+@dataclass
+class BatchWorkload:
+    """Many independent IOD problems of uneven size."""
+    name: str
+    mu: float
+    h: float
+    sigma: float
+    chief: np.ndarray          # [P, 6]
+    truth: np.ndarray          # [P, 6]
+    t: list                    # P arrays [K_p]
+    noise: list                # P arrays [K_p, 2]
+    m: np.ndarray              # [P] particles
+    n_iter: int
+    lo: np.ndarray             # [P, 6]
+    hi: np.ndarray             # [P, 6]
+    omega: float = 0.7
+    eta1: float = 1.5
+    eta2: float = 1.5
+    pso_seed: int = 0
+
+    @property
+    def P(self) -> int:
+        return len(self.m)
+
+    @property
+    def K(self) -> np.ndarray:
+        return np.array([len(t) for t in self.t])
+
+    def steps(self) -> np.ndarray:
+        """RK4 steps per evaluation (all times lie on the h grid)."""
+        return np.array([int(round(t[-1] / self.h)) for t in self.t], dtype=np.int64)
+
+    def particle_steps(self) -> int:
+        return int(self.n_iter) * int(np.sum(self.m * self.steps()))
+
+
+def c2(seed: int = 0, P: int = 1024, n_iter: int = 150, m_range=(512, 8192),
+       K_range=(5, 80), T_range=(0.2, 3.0), h: float = 1e-3, sigma: float = 1e-5) -> BatchWorkload:
+    """Batched uneven problems: chief x = L1 or L2 + U(+-0.02), y = 0,
+    z ~ U(+-0.1), velocity uniform in a ball of radius 0.3; K ~ U{5..80};
+    arc T ~ U(0.2, 3.0) snapped to a multiple of K h; m log-uniform in
+    [512, 8192]; deputy offsets, box and sigma as the small case; h = 1e-3,
+    150 iterations."""
+    rng = np.random.default_rng([seed, 4])
+    chief = np.zeros((P, 6))
+    truth = np.zeros((P, 6))
+    ts, noise = [], []
+    m = np.zeros(P, dtype=np.int64)
+    for p in range(P):
+        base = L1_X if rng.random() < 0.5 else L2_X
+        chief[p, 0] = base + rng.uniform(-0.02, 0.02)
+        chief[p, 2] = rng.uniform(-0.1, 0.1)
+        chief[p, 3:] = uniform_ball(rng, 0.3)
+        truth[p] = chief[p]
+        truth[p, :3] += uniform_ball(rng, 1e-3)
+        truth[p, 3:] += rng.uniform(-1e-3, 1e-3, 3)
+        K = int(rng.integers(K_range[0], K_range[1] + 1))
+        T = rng.uniform(*T_range)
+        per = max(1, int(round(T / (K * h))))   # whole steps between observations
+        ts.append(np.arange(1, K + 1, dtype=np.float64) * (per * h))
+        noise.append(rng.standard_normal((K, 2)) * sigma)
+        m[p] = int(round(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+    return BatchWorkload(f"c2_P{P}_N{n_iter}", MU_EARTH_MOON, h, sigma, chief, truth, ts, noise,
+                         m, n_iter, chief - 2e-3, chief + 2e-3, pso_seed=seed)

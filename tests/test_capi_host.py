@@ -94,7 +94,7 @@ def test_calls_reject_null_handle_and_bad_shapes():
     assert L.iod_num_obs(None) == iod.IOD_EINVAL
     assert L.iod_swarm_work_len(0) == iod.IOD_EINVAL
     assert L.iod_swarm_work_len(1) > 0
-    assert L.iod_swarm_work_len(65536) == 2 * 256 * 8 + 16
+    assert L.iod_swarm_work_len(65536) == 2 * 1024 * 8 + 16
     p = iod.pso_params(0.7, 1.5, 1.5, 0, np.zeros(6), np.ones(6))
     assert L.iod_solve(None, C.byref(p), 10, 10, None, None, None) == iod.IOD_EINVAL
     assert L.iod_step(None, None, C.byref(p), 1, None) == iod.IOD_EINVAL
