@@ -107,6 +107,63 @@ def cpu_baseline(wl, obs, target_s):
                       f"{el:.1f} s wall"}
 
 
+def run_batch(args, iod, torch):
+    """The uneven batch: every problem solved by its own swarm, one launch per
+    iteration for the whole batch, launch configuration from the autotuner."""
+    from paper_2207_13175_amd import workloads as W
+    wl = W.c2(0)
+    if args.iters is not None:
+        wl.n_iter = args.iters
+    obs = []
+    for p in range(wl.P):
+        one = W.Workload("p", wl.mu, wl.h, wl.sigma, wl.chief[p], wl.truth[p], wl.t[p], wl.noise[p],
+                         1, 1)
+        obs.append(observed_angles(iod, torch, one))
+    print(f"# observations simulated for {wl.P} problems", file=sys.stderr, flush=True)
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+              for p in range(wl.P)]
+    cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3)
+    print(f"# autotuned: block {cfg.block} order {cfg.order} graph {cfg.graph}", file=sys.stderr,
+          flush=True)
+    steps = iod.iod_batch_steps(b)
+    for _ in range(args.warmup):
+        iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+    torch.cuda.synchronize()
+    iter_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g, J, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+        iter_ms.append(iod.iod_batch_last_iter_ms(b))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ps_per_solve = int(wl.n_iter) * int(np.sum(wl.m * steps))
+    flop_launch = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
+    launch_s = float(np.mean(iter_ms)) * 1e-3
+    achieved = flop_launch / launch_s / 1e12
+    err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
+    return {
+        "metric": METRIC, "value": args.steps * ps_per_solve / elapsed, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "problems": wl.P, "particles": int(wl.m.sum()),
+                   "iterations": wl.n_iter, "obs_range": [int(wl.K.min()), int(wl.K.max())],
+                   "steps_range": [int(steps.min()), int(steps.max())], "h": wl.h,
+                   "particle_steps_per_solve": ps_per_solve,
+                   "batch_solves_per_s": args.steps / elapsed,
+                   "problem_solves_per_s": args.steps * wl.P / elapsed,
+                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph},
+                   "autotune_ms_per_iter": [round(float(v), 3) for v in cand_ms],
+                   "median_pos_err_lu": float(np.median(err)),
+                   "finite_costs": int(np.sum(np.isfinite(J)))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_swarm_iter (batched)", "avg_launch_ms": launch_s * 1e3,
+                     "flop_per_launch": flop_launch},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +188,10 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.workload == "c2":
+        print(json.dumps(run_batch(args, iod, torch)), flush=True)
+        return
 
     wl = make_workload(args.workload)
     if args.iters is not None:

@@ -283,6 +283,12 @@ int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, 
 int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
                     double *best_states, double *best_costs, double *history);
 
+/* Mean device time (ms) of one iteration launch in the last iod_batch_solve
+ * on b, measured with HIP events on the solve's stream around iterations
+ * 2 .. n_iter (the first iteration reuses the initial evaluation); 0 if that
+ * solve ran fewer than 2 iterations, a negative code for a NULL batch. */
+double iod_batch_last_iter_ms(const iod_batch *b);
+
 /* Time trial_iters iterations of the batch under each candidate launch
  * configuration (workgroup size 64/128/256 x longest-first/problem order x
  * graph on/off), keep the fastest as the batch's configuration and return it

@@ -97,6 +97,7 @@ _SIGNATURES = {
     "iod_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64, _D, _D, _D]),
     "iod_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
                                      C.POINTER(iod_launch_config), _D, C.POINTER(C.c_int32)]),
+    "iod_batch_last_iter_ms": (C.c_double, [C.c_void_p]),
 }
 
 _lib = None
@@ -401,3 +402,10 @@ def iod_batch_autotune(batch: Batch, params, m, trial_iters=4):
     _check(lib().iod_batch_autotune(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
                                     int(trial_iters), C.byref(cfg), _dp(ms), C.byref(n)))
     return cfg, ms[:n.value]
+
+
+def iod_batch_last_iter_ms(batch: Batch) -> float:
+    v = lib().iod_batch_last_iter_ms(batch.ptr)
+    if v < 0:
+        raise IodError(int(v), iod_last_error())
+    return v

@@ -246,6 +246,7 @@ struct iod_batch {
     double *d_tab = nullptr;       // concatenated [sum K][TAB_W]
     int32_t *d_ns = nullptr;       // concatenated [sum K]
     iod_launch_config cfg{0, IOD_ORDER_LONGEST_FIRST, 1, 0};
+    double last_iter_ms = 0.0;  // mean iteration time of the last iod_batch_solve
 
     KArgs kargs(int32_t p) const
     {
@@ -909,7 +910,15 @@ int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m
     if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
     if (rc != IOD_OK) return rc;
     if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
-    return batch_run(b, params, m, n_iter, b->cfg, best_states, best_costs, history, nullptr);
+    b->last_iter_ms = 0.0;
+    return batch_run(b, params, m, n_iter, b->cfg, best_states, best_costs, history,
+                     n_iter >= 2 ? &b->last_iter_ms : nullptr);
+}
+
+double iod_batch_last_iter_ms(const iod_batch *b)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    return b->last_iter_ms;
 }
 
 int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
