@@ -107,9 +107,12 @@ def cpu_baseline(wl, obs, target_s):
                       f"{el:.1f} s wall"}
 
 
-def run_batch(args, iod, torch):
+def run_batch(args, iod, torch, top_k=0):
     """The uneven batch: every problem solved by its own swarm, one launch per
-    iteration for the whole batch, launch configuration from the autotuner."""
+    iteration for the whole batch, launch configuration from the autotuner.
+    top_k > 0: mixed precision (FP32 ranking, FP64 re-evaluation of the top_k
+    personal bests per problem per iteration), compared with an untimed FP64
+    solve of the same batch."""
     from paper_2207_13175_amd import workloads as W
     wl = W.c2(0)
     if args.iters is not None:
@@ -123,20 +126,39 @@ def run_batch(args, iod, torch):
     b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
               for p in range(wl.P)]
-    cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3)
+    cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
     print(f"# autotuned: block {cfg.block} order {cfg.order} graph {cfg.graph}", file=sys.stderr,
           flush=True)
     steps = iod.iod_batch_steps(b)
+
+    def solve():
+        if top_k:
+            return iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=top_k, history=False)
+        return iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+
     for _ in range(args.warmup):
-        iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+        solve()
     torch.cuda.synchronize()
     iter_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g, J, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+        g, J, _ = solve()
         iter_ms.append(iod.iod_batch_last_iter_ms(b))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    compare = None
+    if top_k:
+        # the FP64 swarm on the same batch, untimed, for the error statement
+        g64, J64, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+        dstate = np.max(np.abs(g - g64), axis=1)
+        e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
+        emx = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
+        ratio = J / J64
+        q = lambda a: [float(np.quantile(a, v)) for v in (0.1, 0.5, 0.9)]
+        compare = {"state_diff_vs_fp64_q10_50_90": q(dstate),
+                   "cost_ratio_vs_fp64_q10_50_90": q(ratio),
+                   "pos_err_mixed_q10_50_90": q(emx), "pos_err_fp64_q10_50_90": q(e64),
+                   "same_best_state": int(np.sum(dstate == 0))}
     ps_per_solve = int(wl.n_iter) * int(np.sum(wl.m * steps))
     flop_launch = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
     launch_s = float(np.mean(iter_ms)) * 1e-3
@@ -145,9 +167,10 @@ def run_batch(args, iod, torch):
     return {
         "metric": METRIC, "value": args.steps * ps_per_solve / elapsed, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "problems": wl.P, "particles": int(wl.m.sum()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if top_k else "f64", "data": "synthetic",
+        "config": {"workload": wl.name + (f"_mixed_top{top_k}" if top_k else ""),
+                   "mixed_vs_fp64": compare, "problems": wl.P, "particles": int(wl.m.sum()),
                    "iterations": wl.n_iter, "obs_range": [int(wl.K.min()), int(wl.K.max())],
                    "steps_range": [int(steps.min()), int(steps.max())], "h": wl.h,
                    "particle_steps_per_solve": ps_per_solve,
@@ -189,8 +212,9 @@ def main():
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    if args.workload == "c2":
-        print(json.dumps(run_batch(args, iod, torch)), flush=True)
+    if args.workload in ("c2", "c3"):
+        top_k = 64 if args.workload == "c3" else 0
+        print(json.dumps(run_batch(args, iod, torch, top_k=top_k)), flush=True)
         return
 
     wl = make_workload(args.workload)

@@ -289,16 +289,56 @@ int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m
  * solve ran fewer than 2 iterations, a negative code for a NULL batch. */
 double iod_batch_last_iter_ms(const iod_batch *b);
 
+/* ------------------------------------------------------------------------ */
+/* Mixed precision: the swarm is ranked with FP32 propagation and the global */
+/* best is decided by FP64 re-evaluation (a systems variant of Algorithm 1;  */
+/* the paper itself works in double precision throughout).                 */
+/* ------------------------------------------------------------------------ */
+
+/* As iod_propagate, with FP32 arithmetic: RK4 stages in FP32 (1/r^3 from the
+ * hardware reciprocal square root), the state increment accumulated with
+ * Kahan compensation; states written as FP64 (state - compensation).
+ * Errors: as iod_propagate. */
+int iod_propagate_f32(iod_handle *h, const double *x, int64_t ld, int64_t m, double *states,
+                      void *stream);
+
+/* As iod_batch_eval, with the FP32 propagation above and the residual formed
+ * from the compensated state minus the chief position split into an FP32
+ * pair; e_k in FP32, J accumulated in FP64. Synchronises `stream`. */
+int iod_batch_eval_f32(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                       void *stream);
+
+/* For every problem, the top_k (1 <= top_k <= 256) particle indices with the
+ * smallest (cost, index), NaN ranked as +inf, in ascending order.
+ *   keys  device [ld], columns per iod_batch_offsets
+ *   out   device [P][top_k]; entries past m[p] are -1
+ * Synchronises `stream`. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+int iod_batch_select_topk(iod_batch *b, const double *keys, int64_t ld, const int64_t *m,
+                          int32_t top_k, int32_t *out, void *stream);
+
+/* Mixed-precision solve: as iod_batch_solve, but each evaluation of the
+ * swarm uses the FP32 fitness (personal bests compare FP32 costs); after
+ * initialisation and after every iteration the top_k personal bests of each
+ * problem (1 <= top_k <= 256) are re-evaluated in FP64, and the global best
+ * moves to the lowest of them if its FP64 cost is strictly lower. The
+ * velocity update pulls towards that FP64-decided global best. Reported
+ * best states and costs (and history) are FP64: best_costs[p] is the FP64
+ * cost of best_states[p]. Synchronous. */
+int iod_batch_solve_mixed(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                          int64_t n_iter, int32_t top_k, double *best_states, double *best_costs,
+                          double *history);
+
 /* Time trial_iters iterations of the batch under each candidate launch
  * configuration (workgroup size 64/128/256 x longest-first/problem order x
- * graph on/off), keep the fastest as the batch's configuration and return it
- * in *chosen. If ms_per_iter is given it receives the mean time per
+ * graph on/off), for the FP64 solve (top_k = 0) or the mixed-precision solve
+ * with that top_k, keep the fastest as the batch's configuration and return
+ * it in *chosen. If ms_per_iter is given it receives the mean time per
  * iteration of each candidate, in the order block-major, then order, then
  * graph (12 values); *n_candidates receives the count. Synchronous.
  * Errors: as iod_batch_solve. */
 int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
-                       int64_t trial_iters, iod_launch_config *chosen, double *ms_per_iter,
-                       int32_t *n_candidates);
+                       int64_t trial_iters, int32_t top_k, iod_launch_config *chosen,
+                       double *ms_per_iter, int32_t *n_candidates);
 
 #ifdef __cplusplus
 }

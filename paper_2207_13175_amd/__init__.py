@@ -96,8 +96,15 @@ _SIGNATURES = {
     "iod_batch_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_void_p, C.c_void_p]),
     "iod_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64, _D, _D, _D]),
     "iod_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
-                                     C.POINTER(iod_launch_config), _D, C.POINTER(C.c_int32)]),
+                                     C.c_int32, C.POINTER(iod_launch_config), _D,
+                                     C.POINTER(C.c_int32)]),
     "iod_batch_last_iter_ms": (C.c_double, [C.c_void_p]),
+    "iod_propagate_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "iod_batch_eval_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_void_p, C.c_void_p]),
+    "iod_batch_select_topk": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_int32,
+                                        C.c_void_p, C.c_void_p]),
+    "iod_batch_solve_mixed": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
+                                        C.c_int32, _D, _D, _D]),
 }
 
 _lib = None
@@ -393,14 +400,16 @@ def iod_batch_solve(batch: Batch, params, m, n_iter, history=True):
     return st, J, hist
 
 
-def iod_batch_autotune(batch: Batch, params, m, trial_iters=4):
-    """(chosen iod_launch_config, ms per iteration of the 12 candidates)."""
+def iod_batch_autotune(batch: Batch, params, m, trial_iters=4, top_k=0):
+    """(chosen iod_launch_config, ms per iteration of the 12 candidates);
+    top_k = 0 tunes the FP64 solve, top_k > 0 the mixed-precision one."""
     m = np.ascontiguousarray(m, dtype=np.int64)
     cfg = iod_launch_config()
     ms = np.empty(12)
     n = C.c_int32()
     _check(lib().iod_batch_autotune(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
-                                    int(trial_iters), C.byref(cfg), _dp(ms), C.byref(n)))
+                                    int(trial_iters), int(top_k), C.byref(cfg), _dp(ms),
+                                    C.byref(n)))
     return cfg, ms[:n.value]
 
 
@@ -409,3 +418,44 @@ def iod_batch_last_iter_ms(batch: Batch) -> float:
     if v < 0:
         raise IodError(int(v), iod_last_error())
     return v
+
+
+# ----------------------------------------------------------------------------
+# Mixed precision
+# ----------------------------------------------------------------------------
+
+def iod_propagate_f32(handle: Handle, x, m, states, stream=None):
+    """FP32 (Kahan) propagation; x: [6, ld] -> states: [K, 6, ld] (FP64 values)."""
+    ld = x.shape[1]
+    _check(lib().iod_propagate_f32(handle.ptr, _dev(x, (6, ld)), ld, int(m),
+                                   _dev(states, (handle.K, 6, ld)), _stream(stream)))
+
+
+def iod_batch_eval_f32(batch: Batch, x, m, cost, stream=None):
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    ld = x.shape[1]
+    _check(lib().iod_batch_eval_f32(batch.ptr, _dev(x, (6, ld)), ld, m.ctypes.data_as(_I64),
+                                    _dev(cost, (ld,)), _stream(stream)))
+
+
+def iod_batch_select_topk(batch: Batch, keys, m, top_k, out, stream=None):
+    """keys: float64 [ld] -> out: int32 [P, top_k] tensor on the GPU."""
+    import torch
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    if out.dtype != torch.int32 or tuple(out.shape) != (batch.P, int(top_k)) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 [P, top_k] tensor")
+    ld = keys.shape[0]
+    _check(lib().iod_batch_select_topk(batch.ptr, _dev(keys, (ld,)), ld, m.ctypes.data_as(_I64),
+                                       int(top_k), C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def iod_batch_solve_mixed(batch: Batch, params, m, n_iter, top_k=64, history=True):
+    """(best states [P, 6], FP64 best costs [P], history [P, n_iter + 1] or None)."""
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    st = np.empty((batch.P, 6))
+    J = np.empty(batch.P)
+    hist = np.empty((batch.P, int(n_iter) + 1)) if history else None
+    _check(lib().iod_batch_solve_mixed(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
+                                       int(n_iter), int(top_k), _dp(st), _dp(J),
+                                       _dp(hist) if history else None))
+    return st, J, hist

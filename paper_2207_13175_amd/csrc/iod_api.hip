@@ -764,9 +764,11 @@ int batch_layout(const iod_batch *b, const iod_pso_params *params, const int64_t
 }
 
 // Allocates and runs one batched solve; optional timing of the iterations.
+// top_k = 0: FP64 swarm. top_k > 0: FP32 ranking with FP64 re-evaluation of
+// the top_k personal bests per problem each iteration.
 int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
               const iod_launch_config &cfg, double *best_states, double *best_costs,
-              double *history, double *iter_ms)
+              double *history, double *iter_ms, int32_t top_k = 0)
 {
     const int bs = block_of(cfg);
     BatchLayout L;
@@ -775,9 +777,11 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     const int64_t P = b->P, ld = L.ld;
     const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1));
     Stream st;
-    DevBuf dbuf, ddesc, dwork;
+    DevBuf dbuf, ddesc, dwork, dcand;
     HIP_TRY(hipStreamCreate(&st.s));
     HIP_TRY(hipMalloc(&dbuf.p, nd * sizeof(double)));
+    if (top_k > 0) HIP_TRY(hipMalloc(&dcand.p, (size_t)P * top_k * sizeof(int32_t)));
+    int32_t *cand = (int32_t *)dcand.p;
     double *base = (double *)dbuf.p;
     double *hist = base + 20 * ld + 2 * L.total_slots * REC + 2 * P * REC;
     for (int64_t p = 0; p < P; ++p) {
@@ -802,19 +806,31 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     B.total_slots = L.total_slots;
     B.nprob = P;
     const ProbDesc &d0 = L.descs[0];
-    HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st.s));
+    // one iteration: FP64 fused launch, or FP32 launch + top-k + FP64 re-evaluation
+    auto iterate = [&](int64_t n) -> hipError_t {
+        if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st.s);
+        hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, st.s);
+        if (e == hipSuccess) e = launch_topk(B, B.jp, top_k, cand, st.s);
+        if (e == hipSuccess) e = launch_reeval64(B, cand, top_k, n, st.s);
+        return e;
+    };
+    if (top_k == 0) {
+        HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st.s));
+    } else {
+        HIP_TRY(launch_mixed_init(d0, B, bs, L.grid, st.s));
+        HIP_TRY(launch_topk(B, B.jp, top_k, cand, st.s));
+        HIP_TRY(launch_reeval64(B, cand, top_k, 0, st.s));
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (iter_ms) {
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         // the first iteration reuses the initial evaluation: run it untimed
-        HIP_TRY(launch_swarm_iter(d0, B, bs, L.grid, 1, st.s));
+        HIP_TRY(iterate(1));
         HIP_TRY(hipEventRecord(e0, st.s));
     }
     const int64_t n0 = iter_ms ? 1 : 0;
-    rc = run_iterations(st.s, cfg.graph != 0, n0, n_iter - n0, [&](int64_t n) {
-        return launch_swarm_iter(d0, B, bs, L.grid, n, st.s);
-    });
+    rc = run_iterations(st.s, cfg.graph != 0, n0, n_iter - n0, iterate);
     if (rc == IOD_OK && iter_ms) {
         hipError_t e = hipEventRecord(e1, st.s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -825,7 +841,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (rc == IOD_OK) {
+    if (rc == IOD_OK && top_k == 0) {
         hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
         if (e != hipSuccess) rc = hip_fail(e, "final launch");
     }
@@ -866,12 +882,81 @@ int check_batch_swarm_args(const iod_batch *b, const iod_pso_params *params, con
     return IOD_OK;
 }
 
+int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                    void *stream, bool f32);
+
 }  // namespace
 
 extern "C" {
 
 int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
                    void *stream)
+{
+    return batch_eval_impl(b, x, ld, m, cost, stream, false);
+}
+
+int iod_batch_eval_f32(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                       void *stream)
+{
+    return batch_eval_impl(b, x, ld, m, cost, stream, true);
+}
+
+int iod_propagate_f32(iod_handle *h, const double *x, int64_t ld, int64_t m, double *states,
+                      void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, states);
+    if (rc != IOD_OK || m == 0) return rc;
+    HIP_TRY(launch_propagate32(h->kargs(), x, ld, m, states, (hipStream_t)stream));
+    return IOD_OK;
+}
+
+int iod_batch_select_topk(iod_batch *b, const double *keys, int64_t ld, const int64_t *m,
+                          int32_t top_k, int32_t *out, void *stream)
+{
+    int rc = check_batch(b);
+    if (rc != IOD_OK) return rc;
+    if (!m) return fail(IOD_EINVAL, "null m");
+    if (top_k < 1 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [1, %d]", TOPK_MAX);
+    BatchLayout L;
+    rc = batch_layout(b, nullptr, m, 256, b->cfg.order, L);
+    if (rc != IOD_OK) return rc;
+    if (ld < L.ld) return fail(IOD_EINVAL, "ld = %lld < %lld", (long long)ld, (long long)L.ld);
+    if (!keys || !out) return fail(IOD_EINVAL, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf ddesc;
+    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
+    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    SwarmArrays B;
+    std::memset(&B, 0, sizeof B);
+    B.desc = (const ProbDesc *)ddesc.p;
+    B.ld = ld;
+    B.nprob = b->P;
+    HIP_TRY(launch_topk(B, keys, top_k, out, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IOD_OK;
+}
+
+int iod_batch_solve_mixed(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                          int64_t n_iter, int32_t top_k, double *best_states, double *best_costs,
+                          double *history)
+{
+    int rc = check_batch(b);
+    if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
+    if (rc != IOD_OK) return rc;
+    if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    if (top_k < 1 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [1, %d]", TOPK_MAX);
+    b->last_iter_ms = 0.0;
+    return batch_run(b, params, m, n_iter, b->cfg, best_states, best_costs, history,
+                     n_iter >= 2 ? &b->last_iter_ms : nullptr, top_k);
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
+                    void *stream, bool f32)
 {
     int rc = check_batch(b);
     if (rc != IOD_OK) return rc;
@@ -898,10 +983,17 @@ int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, 
     B.ld = ld;
     B.nprob = b->P;
     B.total_slots = L.total_slots;
-    HIP_TRY(launch_eval(L.descs[0], B, bs, L.grid, st));
+    if (f32)
+        HIP_TRY(launch_eval32(L.descs[0], B, bs, L.grid, st));
+    else
+        HIP_TRY(launch_eval(L.descs[0], B, bs, L.grid, st));
     HIP_TRY(hipStreamSynchronize(st));
     return IOD_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
                     double *best_states, double *best_costs, double *history)
@@ -922,13 +1014,14 @@ double iod_batch_last_iter_ms(const iod_batch *b)
 }
 
 int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
-                       int64_t trial_iters, iod_launch_config *chosen, double *ms_per_iter,
-                       int32_t *n_candidates)
+                       int64_t trial_iters, int32_t top_k, iod_launch_config *chosen,
+                       double *ms_per_iter, int32_t *n_candidates)
 {
     int rc = check_batch(b);
     if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
     if (rc != IOD_OK) return rc;
     if (trial_iters < 2) return fail(IOD_EINVAL, "trial_iters must be >= 2");
+    if (top_k < 0 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [0, %d]", TOPK_MAX);
     const int blocks[3] = {64, 128, 256};
     iod_launch_config best{256, IOD_ORDER_LONGEST_FIRST, 1, 0};
     double best_ms = INFINITY;
@@ -938,7 +1031,7 @@ int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t
             for (int graph = 0; graph < 2; ++graph) {
                 iod_launch_config cfg{blocks[bi], order, graph, 0};
                 double ms = 0;
-                rc = batch_run(b, params, m, trial_iters, cfg, nullptr, nullptr, nullptr, &ms);
+                rc = batch_run(b, params, m, trial_iters, cfg, nullptr, nullptr, nullptr, &ms, top_k);
                 if (rc != IOD_OK) return rc;
                 if (ms_per_iter) ms_per_iter[c] = ms;
                 ++c;
