@@ -83,6 +83,12 @@ def _load():
                                     C.c_int64, C.c_int64,
                                     _D, _D, _D, _D, _D, _D, _D, _I64, _D]
     lib.orc_pso_iterate.restype = C.c_int
+    lib.orc_rhs_jac.argtypes = [C.c_double, _D, _D]
+    lib.orc_rk4_step_tangent.argtypes = [C.c_double, C.c_double, _D, _D]
+    lib.orc_residuals.argtypes = [C.POINTER(_Problem), _D, _D, _D]
+    lib.orc_residuals.restype = C.c_int
+    lib.orc_grad.argtypes = [C.POINTER(_Problem), _D, _D, _D]
+    lib.orc_grad.restype = C.c_int
     _lib = lib
     return lib
 
@@ -264,3 +270,45 @@ def pso_solve(problem: Problem, pso: Pso, m: int, n_iter: int):
     h0 = s.jg.value
     hist = pso_iterate(problem, pso, s, n_iter)
     return s.g.copy(), s.jg.value, np.concatenate([[h0], hist]), s
+
+
+def rhs_jac(mu, s):
+    """Jacobian [6, 6] of the equations of motion at s."""
+    lib = _load()
+    s = _f64(s).ravel()
+    A = np.empty((6, 6))
+    lib.orc_rhs_jac(float(mu), _dp(s), _dp(A))
+    return A
+
+
+def rk4_step_tangent(mu, h, s, phi):
+    """(next state [6], d(next)/d(s) @ phi [6, 6]) for one RK4 step."""
+    lib = _load()
+    X = _f64(s).ravel().copy()
+    Phi = _f64(phi, (6, 6)).copy()
+    lib.orc_rk4_step_tangent(float(mu), float(h), _dp(X), _dp(Phi))
+    return X, Phi
+
+
+def residuals(problem: Problem, x0, jacobian=False):
+    """Whitened residuals [2K] (azimuth, elevation per observation, divided by
+    sigma) and, if asked, their Jacobian [2K, 6] from the RK4 tangent."""
+    lib = _load()
+    x0 = _f64(x0).ravel()
+    r = np.empty(2 * problem.K)
+    jac = np.empty((2 * problem.K, 6)) if jacobian else None
+    rc = lib.orc_residuals(C.byref(problem._s), _dp(x0), _dp(r), _dp(jac) if jacobian else None)
+    if rc < 0:
+        raise ValueError("invalid problem")
+    return (r, jac) if jacobian else r
+
+
+def grad(problem: Problem, x0):
+    """(gradient [6] of the cost at x0 from forward sensitivities, cost)."""
+    lib = _load()
+    x0 = _f64(x0).ravel()
+    g = np.empty(6)
+    J = C.c_double()
+    if lib.orc_grad(C.byref(problem._s), _dp(x0), _dp(g), C.byref(J)) < 0:
+        raise ValueError("invalid problem")
+    return g, J.value

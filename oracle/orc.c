@@ -509,3 +509,186 @@ int orc_pso_iterate(const orc_problem *P, const orc_pso *S, int64_t m,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sensitivities: the exact tangent of the discrete RK4 map (forward        */
+/* sensitivities / state transition matrix), residual Jacobians and the     */
+/* cost gradient. Used to check the GPU adjoint and the Gauss-Newton polish  */
+/* that replaces the paper's Levenberg-Marquardt local minimisation (Local  */
+/* Minimization: min ||F||^2 over the deputy initial state).                */
+/* ------------------------------------------------------------------------ */
+
+/* Jacobian A = df/ds of the CR3BP right-hand side, row-major 6x6:
+ * [[0, I], [d a/d r, d a/d v]] with d a/d v = [[0, 2, 0], [-2, 0, 0], [0, 0, 0]]
+ * and, with c_j = mu_j / r_j^3 and e_j = 3 mu_j / r_j^5 (mu_1 = 1 - mu,
+ * mu_2 = mu, d_j the offset from primary j):
+ *   d a/d r = diag(1, 1, 0) - (c1 + c2) I + e1 d1 d1^T + e2 d2 d2^T. */
+void orc_rhs_jac(double mu, const double s[6], double A[36])
+{
+    const double mu1 = 1.0 - mu;
+    const double x = s[0], y = s[1], z = s[2];
+    const double p1[3] = {x + mu, y, z};
+    const double p2[3] = {x - mu1, y, z};
+    const double r1 = sqrt(p1[0] * p1[0] + y * y + z * z);
+    const double r2 = sqrt(p2[0] * p2[0] + y * y + z * z);
+    const double c1 = mu1 / (r1 * r1 * r1), c2 = mu / (r2 * r2 * r2);
+    const double e1 = 3.0 * mu1 / pow(r1, 5), e2 = 3.0 * mu / pow(r2, 5);
+    int i, j;
+    for (i = 0; i < 36; i++) A[i] = 0.0;
+    for (i = 0; i < 3; i++) A[6 * i + 3 + i] = 1.0;
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++)
+            A[6 * (3 + i) + j] = e1 * p1[i] * p1[j] + e2 * p2[i] * p2[j] - (i == j ? c1 + c2 : 0.0);
+    A[6 * 3 + 0] += 1.0;
+    A[6 * 4 + 1] += 1.0;
+    A[6 * 3 + 4] = 2.0;
+    A[6 * 4 + 3] = -2.0;
+}
+
+static void matmul6(const double A[36], const double B[36], double C[36])
+{
+    int i, j, k;
+    for (i = 0; i < 6; i++)
+        for (j = 0; j < 6; j++) {
+            double acc = 0.0;
+            for (k = 0; k < 6; k++) acc += A[6 * i + k] * B[6 * k + j];
+            C[6 * i + j] = acc;
+        }
+}
+
+/* One RK4 step of X (as orc_rk4_step) together with the derivative of the
+ * discrete step map applied to Phi (6x6, row-major): with the stage inputs
+ * s_i and dS_1 = Phi, dK_i = A(s_i) dS_i, dS_2 = Phi + h/2 dK_1,
+ * dS_3 = Phi + h/2 dK_2, dS_4 = Phi + h dK_3,
+ *   Phi <- Phi + h/6 (dK_1 + 2 dK_2 + 2 dK_3 + dK_4). */
+void orc_rk4_step_tangent(double mu, double h, double X[6], double Phi[36])
+{
+    double s[6], k[6], A[36], dS[36], dK[36], acc[36];
+    const double hs[4] = {0.0, 0.5 * h, 0.5 * h, h};
+    const double wt[4] = {1.0, 2.0, 2.0, 1.0};
+    double ks[4][6];
+    int st, i;
+    for (i = 0; i < 36; i++) {
+        acc[i] = 0.0;
+        dS[i] = Phi[i];
+    }
+    for (i = 0; i < 6; i++) s[i] = X[i];
+    for (st = 0; st < 4; st++) {
+        if (st > 0) {
+            for (i = 0; i < 6; i++) s[i] = X[i] + hs[st] * ks[st - 1][i];
+            for (i = 0; i < 36; i++) dS[i] = Phi[i] + hs[st] * dK[i];
+        }
+        orc_rhs(mu, s, k);
+        for (i = 0; i < 6; i++) ks[st][i] = k[i];
+        orc_rhs_jac(mu, s, A);
+        matmul6(A, dS, dK);
+        for (i = 0; i < 36; i++) acc[i] += wt[st] * dK[i];
+    }
+    orc_rk4_step(mu, h, X);
+    for (i = 0; i < 36; i++) Phi[i] += h / 6.0 * acc[i];
+}
+
+/* Derivatives of the residual angles with respect to rho:
+ *   d(da)/d rho = -d(azimuth)/d rho = (rho_y, -rho_x, 0) / rho_xy^2
+ *   d(db)/d rho = -d(elevation)/d rho
+ *               = (rho_z rho_x / rho_xy, rho_z rho_y / rho_xy, -rho_xy) / |rho|^2 */
+static void residual_grad(const double rho[3], double ga[3], double gb[3])
+{
+    const double rxy2 = rho[0] * rho[0] + rho[1] * rho[1];
+    const double rxy = sqrt(rxy2);
+    const double r2 = rxy2 + rho[2] * rho[2];
+    ga[0] = rho[1] / rxy2;
+    ga[1] = -rho[0] / rxy2;
+    ga[2] = 0.0;
+    gb[0] = rho[2] * rho[0] / rxy / r2;
+    gb[1] = rho[2] * rho[1] / rxy / r2;
+    gb[2] = -rxy / r2;
+}
+
+/* Whitened residuals r[2k] = da_k / sigma, r[2k+1] = db_k / sigma at x0 and,
+ * if jac is not NULL, their Jacobian jac[2K][6] with respect to x0 through
+ * the discrete RK4 tangent. Returns 0, -1 on an invalid schedule, 1 if some
+ * line of sight vanishes (residuals there are NaN). */
+int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *jac)
+{
+    tables T;
+    double X[6], Phi[36];
+    int64_t step = 0;
+    int32_t k;
+    int i, d, bad = 0;
+    const double is = 1.0 / P->sigma;
+    if (tables_make(P, &T) != 0) {
+        tables_free(&T);
+        return -1;
+    }
+    memcpy(X, x0, sizeof X);
+    for (i = 0; i < 36; i++) Phi[i] = (i % 7 == 0) ? 1.0 : 0.0;
+    for (k = 0; k < P->n_obs; k++) {
+        double S[6], SP[36], rho[3], da, db;
+        while (step < T.ns[k]) {
+            if (jac)
+                orc_rk4_step_tangent(P->mu, P->h, X, Phi);
+            else
+                orc_rk4_step(P->mu, P->h, X);
+            step++;
+        }
+        memcpy(S, X, sizeof S);
+        memcpy(SP, Phi, sizeof SP);
+        if (T.tau[k] != 0.0) {
+            if (jac)
+                orc_rk4_step_tangent(P->mu, T.tau[k], S, SP);
+            else
+                orc_rk4_step(P->mu, T.tau[k], S);
+        }
+        for (d = 0; d < 3; d++) rho[d] = S[d] - T.rc[3 * k + d];
+        if (residual(rho, T.sa[k], T.ca[k], T.sb[k], T.cb[k], &da, &db) != 0) {
+            da = NAN;
+            db = NAN;
+            bad = 1;
+        }
+        r[2 * k] = da * is;
+        r[2 * k + 1] = db * is;
+        if (jac) {
+            double ga[3], gb[3];
+            residual_grad(rho, ga, gb);
+            for (i = 0; i < 6; i++) {
+                double ja = 0.0, jb = 0.0;
+                for (d = 0; d < 3; d++) {
+                    ja += ga[d] * SP[6 * d + i];
+                    jb += gb[d] * SP[6 * d + i];
+                }
+                jac[6 * (2 * k) + i] = ja * is;
+                jac[6 * (2 * k + 1) + i] = jb * is;
+            }
+        }
+    }
+    tables_free(&T);
+    return bad;
+}
+
+/* Gradient of the cost J at x0 from the forward sensitivities: with
+ * e_k = r_a^2 + r_b^2 (whitened residuals), dJ/dx0 = sum_k g'(e_k) de_k/dx0,
+ * de_k = 2 (r_a dr_a + r_b dr_b), g'(e) = 2e (sum e_k^2) or 1 (sum e_k).
+ * Writes grad[6] and *J; returns as orc_residuals. */
+int orc_grad(const orc_problem *P, const double x0[6], double grad[6], double *J)
+{
+    const int32_t K = P->n_obs;
+    double *r = (double *)malloc(sizeof(double) * 2 * (size_t)K);
+    double *jac = (double *)malloc(sizeof(double) * 12 * (size_t)K);
+    int32_t k;
+    int i;
+    int rc = orc_residuals(P, x0, r, jac);
+    double acc = 0.0;
+    for (i = 0; i < 6; i++) grad[i] = 0.0;
+    for (k = 0; k < K; k++) {
+        const double e = r[2 * k] * r[2 * k] + r[2 * k + 1] * r[2 * k + 1];
+        const double gp = P->cost_mode == ORC_COST_CHI2 ? 1.0 : 2.0 * e;
+        acc += P->cost_mode == ORC_COST_CHI2 ? e : e * e;
+        for (i = 0; i < 6; i++)
+            grad[i] += gp * 2.0 * (r[2 * k] * jac[6 * (2 * k) + i] + r[2 * k + 1] * jac[6 * (2 * k + 1) + i]);
+    }
+    *J = acc;
+    free(r);
+    free(jac);
+    return rc;
+}
