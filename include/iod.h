@@ -340,6 +340,76 @@ int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t
                        int64_t trial_iters, int32_t top_k, iod_launch_config *chosen,
                        double *ms_per_iter, int32_t *n_candidates);
 
+/* ------------------------------------------------------------------------ */
+/* Sensitivities and the local refinement. The paper refines the swarm's     */
+/* best with MATLAB's Levenberg-Marquardt on the per-observation residuals  */
+/* (Local Minimization, eqs. non:linear:lsq and nonlinlsq:cost). Here the   */
+/* refinement is a damped Gauss-Newton on the whitened angle residuals      */
+/* r = (da, db) / sigma, whose objective is the least-squares cost          */
+/* chi2 = sum_k e_k (IOD_COST_CHI2): the Jacobian of the paper's F_k = e_k   */
+/* vanishes at zero residual, that of the whitened residuals does not.      */
+/* ------------------------------------------------------------------------ */
+
+/* Doubles of workspace iod_grad needs for a leading dimension ld (checkpoints
+ * every 64 RK4 steps plus one 64-step segment, 6 doubles each, per column),
+ * or a negative code. */
+int64_t iod_grad_work_len(const iod_handle *h, int64_t ld);
+
+/* Cost (the handle's cost mode) and its gradient with respect to the initial
+ * state, by the discrete adjoint of the RK4 propagation and the angle model:
+ * a forward pass storing the state every 64 steps, then a reverse sweep that
+ * recomputes each 64-step segment and applies the transposed step
+ * derivative, adding each observation's contribution at its step. The
+ * gradient is that of the computed (discrete) cost.
+ *   x     device [6][ld]     cost device [ld]     grad device [6][ld]
+ *   work  device [iod_grad_work_len(h, ld)], caller-owned scratch
+ * A particle with no line of sight at some observation gets NaN.
+ * Errors: IOD_EINVAL, IOD_EDEVICE. */
+int iod_grad(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost, double *grad,
+             double *work, void *stream);
+
+/* Gauss-Newton normal equations of the whitened residuals from the forward
+ * tangent (6x6 state transition matrix) of the RK4 propagation:
+ *   chi2 device [ld]: sum of r^2
+ *   jtj  device [21][ld]: J^T J, upper triangle row by row
+ *        ((0,0),(0,1),...,(0,5),(1,1),...,(5,5))
+ *   jtr  device [6][ld]: J^T r (= half the gradient of chi2)
+ * Errors: IOD_EINVAL, IOD_EDEVICE. */
+int iod_normal_eq(iod_handle *h, const double *x, int64_t ld, int64_t m, double *chi2,
+                  double *jtj, double *jtr, void *stream);
+
+/* Doubles of workspace iod_polish needs for a leading dimension ld. */
+int64_t iod_polish_work_len(const iod_handle *h, int64_t ld);
+
+/* Refine m candidate states in place with n_iter damped Gauss-Newton
+ * (Levenberg-Marquardt) iterations on chi2: the step solves
+ * (J^T J + lambda diag(J^T J)) dx = -grad(chi2)/2, with J^T J from the
+ * forward tangent and grad(chi2) from the adjoint; a trial is kept if its
+ * chi2 is strictly lower (lambda /10), else rejected (lambda x10);
+ * lambda starts at 1e-3.
+ *   x device [6][ld] in/out; chi2 device [ld] out (chi2 of the result)
+ *   work device [iod_polish_work_len(h, ld)]
+ * Errors: IOD_EINVAL, IOD_EDEVICE. */
+int iod_polish(iod_handle *h, double *x, int64_t ld, int64_t m, int32_t n_iter, double *chi2,
+               double *work, void *stream);
+
+/* Batched polish: candidates of problem p in the columns given by
+ * iod_batch_offsets(m). Synchronises `stream`. */
+int64_t iod_batch_polish_work_len(const iod_batch *b, int64_t ld);
+int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int32_t n_iter,
+                     double *chi2, double *work, void *stream);
+
+/* Swarm then refinement, for every problem of the batch: n_iter iterations of
+ * the particle swarm (FP64 if top_k = 0, else mixed precision with top_k as
+ * in iod_batch_solve_mixed), then n_gn Gauss-Newton iterations on each of the
+ * problem's n_cand (1..64) lowest-cost personal bests, keeping the one with
+ * the lowest chi2. Outputs (host): best_states [P][6], best_chi2 [P] (may be
+ * NULL) and best_costs [P] (the problem's own cost mode, may be NULL).
+ * Synchronous. */
+int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                             int64_t n_iter, int32_t top_k, int32_t n_cand, int32_t n_gn,
+                             double *best_states, double *best_chi2, double *best_costs);
+
 #ifdef __cplusplus
 }
 #endif

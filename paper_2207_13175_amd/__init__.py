@@ -105,6 +105,19 @@ _SIGNATURES = {
                                         C.c_void_p, C.c_void_p]),
     "iod_batch_solve_mixed": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
                                         C.c_int32, _D, _D, _D]),
+    "iod_grad_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
+    "iod_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "iod_normal_eq": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "iod_polish_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
+    "iod_polish": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
+                             C.c_void_p, C.c_void_p]),
+    "iod_batch_polish_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
+    "iod_batch_polish": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
+    "iod_batch_solve_polished": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
+                                           C.c_int32, C.c_int32, C.c_int32, _D, _D, _D]),
 }
 
 _lib = None
@@ -459,3 +472,105 @@ def iod_batch_solve_mixed(batch: Batch, params, m, n_iter, top_k=64, history=Tru
                                        int(n_iter), int(top_k), _dp(st), _dp(J),
                                        _dp(hist) if history else None))
     return st, J, hist
+
+
+# ----------------------------------------------------------------------------
+# Sensitivities, refinement, autograd
+# ----------------------------------------------------------------------------
+
+def _workspace(n, device):
+    import torch
+    return torch.empty(max(int(n), 1), dtype=torch.float64, device=device)
+
+
+def iod_grad(handle: Handle, x, m, cost, grad, work=None, stream=None):
+    """Adjoint gradient: x [6, ld] -> cost [ld], grad [6, ld]. work: float64
+    [iod_grad_work_len] (allocated here if None)."""
+    ld = x.shape[1]
+    if work is None:
+        work = _workspace(_check(lib().iod_grad_work_len(handle.ptr, ld)), x.device)
+    _check(lib().iod_grad(handle.ptr, _dev(x, (6, ld)), ld, int(m), _dev(cost, (ld,)),
+                          _dev(grad, (6, ld)), _dev(work), _stream(stream)))
+
+
+def iod_normal_eq(handle: Handle, x, m, chi2, jtj, jtr, stream=None):
+    """x [6, ld] -> chi2 [ld], jtj [21, ld], jtr [6, ld]."""
+    ld = x.shape[1]
+    _check(lib().iod_normal_eq(handle.ptr, _dev(x, (6, ld)), ld, int(m), _dev(chi2, (ld,)),
+                               _dev(jtj, (21, ld)), _dev(jtr, (6, ld)), _stream(stream)))
+
+
+def iod_polish(handle: Handle, x, m, n_iter, chi2, work=None, stream=None):
+    """Gauss-Newton refinement of the columns of x [6, ld] in place; chi2 [ld] out."""
+    ld = x.shape[1]
+    if work is None:
+        work = _workspace(_check(lib().iod_polish_work_len(handle.ptr, ld)), x.device)
+    _check(lib().iod_polish(handle.ptr, _dev(x, (6, ld)), ld, int(m), int(n_iter),
+                            _dev(chi2, (ld,)), _dev(work), _stream(stream)))
+
+
+def iod_batch_polish(batch: Batch, x, m, n_iter, chi2, work=None, stream=None):
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    ld = x.shape[1]
+    if work is None:
+        work = _workspace(_check(lib().iod_batch_polish_work_len(batch.ptr, ld)), x.device)
+    _check(lib().iod_batch_polish(batch.ptr, _dev(x, (6, ld)), ld, m.ctypes.data_as(_I64),
+                                  int(n_iter), _dev(chi2, (ld,)), _dev(work), _stream(stream)))
+
+
+def iod_batch_solve_polished(batch: Batch, params, m, n_iter, top_k=64, n_cand=16, n_gn=10):
+    """(best states [P, 6], best chi2 [P], best costs [P]) after the swarm and
+    the Gauss-Newton refinement of each problem's n_cand best personal bests."""
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    st = np.empty((batch.P, 6))
+    chi2 = np.empty(batch.P)
+    cost = np.empty(batch.P)
+    _check(lib().iod_batch_solve_polished(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
+                                          int(n_iter), int(top_k), int(n_cand), int(n_gn),
+                                          _dp(st), _dp(chi2), _dp(cost)))
+    return st, chi2, cost
+
+
+def _make_cost_function():
+    import torch
+
+    class IODCost(torch.autograd.Function):
+        """Cost of each particle (rows of x [m, 6], float64 on the GPU) with
+        the gradient from the library's discrete adjoint."""
+
+        @staticmethod
+        def forward(ctx, x, handle):
+            m = x.shape[0]
+            ld = (m + 63) // 64 * 64
+            xs = torch.zeros((6, ld), dtype=torch.float64, device=x.device)
+            xs[:, :m] = x.detach().t()
+            cost = torch.empty(ld, dtype=torch.float64, device=x.device)
+            iod_eval_swarm(handle, xs, m, cost)
+            ctx.handle = handle
+            ctx.save_for_backward(x.detach())
+            return cost[:m].clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            (x,) = ctx.saved_tensors
+            m = x.shape[0]
+            ld = (m + 63) // 64 * 64
+            xs = torch.zeros((6, ld), dtype=torch.float64, device=x.device)
+            xs[:, :m] = x.t()
+            cost = torch.empty(ld, dtype=torch.float64, device=x.device)
+            grad = torch.empty((6, ld), dtype=torch.float64, device=x.device)
+            iod_grad(ctx.handle, xs, m, cost, grad)
+            return grad[:, :m].t() * g[:, None], None
+
+    return IODCost
+
+
+_IODCost = None
+
+
+def iod_cost(x, handle: Handle):
+    """Differentiable cost: torch float64 [m, 6] on the GPU -> [m]."""
+    global _IODCost
+    if _IODCost is None:
+        _IODCost = _make_cost_function()
+    return _IODCost.apply(x, handle)

@@ -766,9 +766,19 @@ int batch_layout(const iod_batch *b, const iod_pso_params *params, const int64_t
 // Allocates and runs one batched solve; optional timing of the iterations.
 // top_k = 0: FP64 swarm. top_k > 0: FP32 ranking with FP64 re-evaluation of
 // the top_k personal bests per problem each iteration.
+// Optional last stage of a batched solve: Gauss-Newton polish of each
+// problem's n_cand best personal bests.
+struct PolishStage {
+    int32_t n_cand, n_gn;
+    double *best_states, *best_chi2, *best_costs;  // host [P][6], [P], [P]
+};
+int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
+                     const PolishStage &S, hipStream_t st);
+
 int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
               const iod_launch_config &cfg, double *best_states, double *best_costs,
-              double *history, double *iter_ms, int32_t top_k = 0)
+              double *history, double *iter_ms, int32_t top_k = 0,
+              const PolishStage *stage = nullptr)
 {
     const int bs = block_of(cfg);
     BatchLayout L;
@@ -845,6 +855,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
         hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
         if (e != hipSuccess) rc = hip_fail(e, "final launch");
     }
+    if (rc == IOD_OK && stage) rc = polish_stage_run(b, L, B, *stage, st.s);
     if (rc == IOD_OK && (best_states || best_costs)) {
         std::vector<double> recs((size_t)P * REC);
         hipError_t e = hipMemcpyAsync(recs.data(), B.recs + (n_iter & 1) * P * REC, recs.size() * sizeof(double),
@@ -1044,6 +1055,280 @@ int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t
     b->cfg = best;
     if (chosen) *chosen = best;
     return IOD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Sensitivities and the Gauss-Newton polish
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Adjoint scratch rows (of 6 doubles per column) for one problem.
+int64_t adj_rows(const HostProblem &P)
+{
+    const int64_t S = P.ns[P.K - 1];
+    return (S + ADJ_CKPT - 1) / ADJ_CKPT + ADJ_CKPT;
+}
+
+// Doubles of polish workspace per column besides the adjoint rows:
+// jtj 21, jtr 6, grad 6, trial 6, chi2 at trial 1, damping 1, cost 1.
+constexpr int64_t POLISH_COLS = 42;
+
+// Damped Gauss-Newton on the columns of B.x (in place): the normal matrix
+// from the forward tangent, the gradient from the discrete adjoint; d0 / the
+// descriptors in B must carry the least-squares cost (mode 1).
+int polish_run(const ProbDesc &d0, SwarmArrays B, int bs, int64_t grid, int32_t n_iter,
+               double *chi2, double *work, int64_t ld, hipStream_t st)
+{
+    double *jtj = work;
+    double *jtr = jtj + 21 * ld;
+    double *g = jtr + 6 * ld;
+    double *xt = g + 6 * ld;
+    double *chi2t = xt + 6 * ld;
+    double *lam = chi2t + ld;
+    double *cost = lam + ld;
+    double *adj = cost + ld;
+    double *x = B.x;
+    HIP_TRY(launch_fill_cols(d0, B, bs, grid, lam, 1e-3, st));
+    for (int32_t it = 0; it < n_iter; ++it) {
+        B.x = x;
+        HIP_TRY(launch_normal(d0, B, bs, grid, chi2, jtj, jtr, st));
+        B.cost = cost;
+        HIP_TRY(launch_grad(d0, B, bs, grid, g, adj, ld, 1, st));
+        HIP_TRY(launch_gn_solve(d0, B, bs, grid, jtj, g, 0.5, lam, xt, st));
+        B.x = xt;
+        B.cost = chi2t;
+        HIP_TRY(launch_eval(d0, B, bs, grid, st));
+        B.x = x;
+        HIP_TRY(launch_gn_accept(d0, B, bs, grid, xt, chi2, chi2t, lam, st));
+    }
+    if (n_iter == 0) {
+        B.x = x;
+        HIP_TRY(launch_normal(d0, B, bs, grid, chi2, jtj, jtr, st));
+    }
+    return IOD_OK;
+}
+
+int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
+                     const PolishStage &S, hipStream_t st)
+{
+    const int64_t P = b->P, stride = 64, ldp = P * stride;
+    int64_t rows = 0;
+    for (const HostProblem &Pb : b->probs) rows = std::max(rows, adj_rows(Pb));
+    DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc;
+    HIP_TRY(hipMalloc(&dcand.p, (size_t)P * S.n_cand * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&dx.p, (size_t)6 * ldp * sizeof(double)));
+    HIP_TRY(hipMalloc(&dchi.p, (size_t)ldp * sizeof(double)));
+    HIP_TRY(hipMalloc(&dwork.p, (size_t)(POLISH_COLS + rows * 6) * ldp * sizeof(double)));
+    HIP_TRY(hipMalloc(&ddesc.p, (size_t)P * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dedesc.p, (size_t)P * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dlist.p, (size_t)P * 2 * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&dn.p, (size_t)P * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&dbest.p, (size_t)6 * P * sizeof(double)));
+    HIP_TRY(hipMalloc(&dbchi.p, (size_t)P * sizeof(double)));
+    HIP_TRY(hipMalloc(&dcost.p, (size_t)P * sizeof(double)));
+    // candidates: the swarm's best personal bests
+    HIP_TRY(launch_topk(B, B.jp, S.n_cand, (int32_t *)dcand.p, st));
+    HIP_TRY(launch_gather(B, (const int32_t *)dcand.p, S.n_cand, (double *)dx.p, ldp, stride, st));
+    std::vector<ProbDesc> pd(L.descs), ed(L.descs);
+    std::vector<int32_t> list(2 * P), n(P);
+    for (int64_t p = 0; p < P; ++p) {
+        ProbDesc &D = pd[p];
+        D.m = std::min<int64_t>(S.n_cand, L.descs[p].m);
+        D.off = p * stride;
+        D.slot_off = 0;
+        D.nslots = 1;
+        D.block = 64;
+        D.hist = nullptr;
+        D.hist_len = 0;
+        D.k.mode = IOD_COST_CHI2;
+        ed[p] = D;
+        ed[p].k.mode = L.descs[p].k.mode;
+        ed[p].m = 1;
+        ed[p].off = p;
+        list[2 * p] = (int32_t)p;
+        list[2 * p + 1] = 0;
+        n[p] = (int32_t)D.m;
+    }
+    HIP_TRY(hipMemcpyAsync(ddesc.p, pd.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dedesc.p, ed.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dlist.p, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dn.p, n.data(), n.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SwarmArrays PB;
+    std::memset(&PB, 0, sizeof PB);
+    PB.desc = (const ProbDesc *)ddesc.p;
+    PB.work = (const int32_t *)dlist.p;
+    PB.x = (double *)dx.p;
+    PB.ld = ldp;
+    PB.nprob = P;
+    int rc = polish_run(pd[0], PB, 64, P, S.n_gn, (double *)dchi.p, (double *)dwork.p, ldp, st);
+    if (rc != IOD_OK) return rc;
+    HIP_TRY(launch_pick_best((const double *)dx.p, (const double *)dchi.p, (const int32_t *)dn.p, P,
+                             ldp, stride, (double *)dbest.p, (double *)dbchi.p, st));
+    // the problem's own cost of each polished best
+    SwarmArrays EB;
+    std::memset(&EB, 0, sizeof EB);
+    EB.desc = (const ProbDesc *)dedesc.p;
+    EB.work = (const int32_t *)dlist.p;
+    EB.x = (double *)dbest.p;
+    EB.cost = (double *)dcost.p;
+    EB.ld = P;
+    EB.nprob = P;
+    HIP_TRY(launch_eval(ed[0], EB, 64, P, st));
+    std::vector<double> best(6 * P), bchi(P), bcost(P);
+    HIP_TRY(hipMemcpyAsync(best.data(), dbest.p, best.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bchi.data(), dbchi.p, bchi.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bcost.data(), dcost.p, bcost.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t p = 0; p < P; ++p) {
+        for (int d = 0; d < 6; ++d) S.best_states[6 * p + d] = best[d * P + p];
+        if (S.best_chi2) S.best_chi2[p] = bchi[p];
+        if (S.best_costs) S.best_costs[p] = bcost[p];
+    }
+    return IOD_OK;
+}
+
+// Single-problem view of m columns of x.
+void single_cols(const iod_handle *h, const double *x, int64_t ld, int64_t m, int bs,
+                 ProbDesc &D, SwarmArrays &B)
+{
+    D = desc_of(h->kargs(), h->P.chief, nullptr);
+    D.m = m;
+    D.nslots = ceil_div(m, bs);
+    D.block = bs;
+    std::memset(&B, 0, sizeof B);
+    B.x = const_cast<double *>(x);
+    B.ld = ld;
+    B.nprob = 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t iod_grad_work_len(const iod_handle *h, int64_t ld)
+{
+    if (!h) return fail(IOD_EINVAL, "null handle");
+    if (ld < 1 || ld > MAX_M) return fail(IOD_EINVAL, "ld out of range");
+    return adj_rows(h->P) * 6 * ld;
+}
+
+int iod_grad(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost, double *grad,
+             double *work, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, cost);
+    if (rc != IOD_OK || m == 0) return rc;
+    if (!grad || !work) return fail(IOD_EINVAL, "null device pointer");
+    const int bs = block_of(h->cfg);
+    ProbDesc D;
+    SwarmArrays B;
+    single_cols(h, x, ld, m, bs, D, B);
+    B.cost = cost;
+    HIP_TRY(launch_grad(D, B, bs, D.nslots, grad, work, ld, -1, (hipStream_t)stream));
+    return IOD_OK;
+}
+
+int iod_normal_eq(iod_handle *h, const double *x, int64_t ld, int64_t m, double *chi2,
+                  double *jtj, double *jtr, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, chi2);
+    if (rc != IOD_OK || m == 0) return rc;
+    if (!jtj || !jtr) return fail(IOD_EINVAL, "null device pointer");
+    const int bs = block_of(h->cfg);
+    ProbDesc D;
+    SwarmArrays B;
+    single_cols(h, x, ld, m, bs, D, B);
+    HIP_TRY(launch_normal(D, B, bs, D.nslots, chi2, jtj, jtr, (hipStream_t)stream));
+    return IOD_OK;
+}
+
+int64_t iod_polish_work_len(const iod_handle *h, int64_t ld)
+{
+    if (!h) return fail(IOD_EINVAL, "null handle");
+    if (ld < 1 || ld > MAX_M) return fail(IOD_EINVAL, "ld out of range");
+    return (POLISH_COLS + adj_rows(h->P) * 6) * ld;
+}
+
+int iod_polish(iod_handle *h, double *x, int64_t ld, int64_t m, int32_t n_iter, double *chi2,
+               double *work, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, chi2);
+    if (rc != IOD_OK || m == 0) return rc;
+    if (!work) return fail(IOD_EINVAL, "null workspace");
+    if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    const int bs = block_of(h->cfg);
+    ProbDesc D;
+    SwarmArrays B;
+    single_cols(h, x, ld, m, bs, D, B);
+    D.k.mode = IOD_COST_CHI2;
+    return polish_run(D, B, bs, D.nslots, n_iter, chi2, work, ld, (hipStream_t)stream);
+}
+
+int64_t iod_batch_polish_work_len(const iod_batch *b, int64_t ld)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    if (ld < 1 || ld > MAX_M) return fail(IOD_EINVAL, "ld out of range");
+    int64_t rows = 0;
+    for (const HostProblem &P : b->probs) rows = std::max(rows, adj_rows(P));
+    return (POLISH_COLS + rows * 6) * ld;
+}
+
+int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int32_t n_iter,
+                     double *chi2, double *work, void *stream)
+{
+    int rc = check_batch(b);
+    if (rc != IOD_OK) return rc;
+    if (!m) return fail(IOD_EINVAL, "null m");
+    if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    const int bs = block_of(b->cfg);
+    BatchLayout L;
+    rc = batch_layout(b, nullptr, m, bs, b->cfg.order, L);
+    if (rc != IOD_OK) return rc;
+    if (ld < L.ld) return fail(IOD_EINVAL, "ld = %lld < %lld", (long long)ld, (long long)L.ld);
+    if (L.grid == 0) return IOD_OK;
+    if (!x || !chi2 || !work) return fail(IOD_EINVAL, "null device pointer");
+    for (ProbDesc &D : L.descs) D.k.mode = IOD_COST_CHI2;
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf ddesc, dwork;
+    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    SwarmArrays B;
+    std::memset(&B, 0, sizeof B);
+    B.desc = (const ProbDesc *)ddesc.p;
+    B.work = (const int32_t *)dwork.p;
+    B.x = x;
+    B.ld = ld;
+    B.nprob = b->P;
+    rc = polish_run(L.descs[0], B, bs, L.grid, n_iter, chi2, work, ld, st);
+    if (rc != IOD_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    return IOD_OK;
+}
+
+// Mixed-precision PSO, then the Gauss-Newton polish of each problem's n_cand
+// best personal bests (by FP32 cost), keeping the best polished candidate.
+int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,
+                             int64_t n_iter, int32_t top_k, int32_t n_cand, int32_t n_gn,
+                             double *best_states, double *best_chi2, double *best_costs)
+{
+    int rc = check_batch(b);
+    if (rc == IOD_OK) rc = check_batch_swarm_args(b, params, m);
+    if (rc != IOD_OK) return rc;
+    if (n_iter < 0 || n_gn < 0) return fail(IOD_EINVAL, "negative iteration count");
+    if (top_k < 0 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [0, %d]", TOPK_MAX);
+    if (n_cand < 1 || n_cand > 64) return fail(IOD_EINVAL, "n_cand must lie in [1, 64]");
+    if (!best_states) return fail(IOD_EINVAL, "null best_states");
+    b->last_iter_ms = 0.0;
+    PolishStage stage{n_cand, n_gn, best_states, best_chi2, best_costs};
+    return batch_run(b, params, m, n_iter, b->cfg, nullptr, nullptr, nullptr,
+                     n_iter >= 2 ? &b->last_iter_ms : nullptr, top_k, &stage);
 }
 
 }  // extern "C"

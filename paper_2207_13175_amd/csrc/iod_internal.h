@@ -92,4 +92,28 @@ hipError_t launch_topk(const SwarmArrays &B, const double *keys, int32_t top_k, 
 hipError_t launch_reeval64(const SwarmArrays &B, const int32_t *cand, int32_t top_k, int64_t n,
                            hipStream_t st);
 
+// Sensitivities. Adjoint scratch per particle column: (ceil(S / 64) + 64)
+// rows of 6 doubles, S the steps of one evaluation; mode >= 0 overrides the
+// cost mode. B.cost receives the cost, grad [6][B.ld] its gradient.
+constexpr int ADJ_CKPT = 64;
+hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st);
+// chi2 [ld], jtj [21][ld], jtr [6][ld] of the whitened residuals.
+hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                         double *chi2, double *jtj, double *jtr, hipStream_t st);
+// Per-column Gauss-Newton step (on B.x) and acceptance, over B's layout.
+hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                           const double *jtj, const double *g, double gscale, const double *lam,
+                           double *xt, hipStream_t st);
+hipError_t launch_gn_accept(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                            const double *xt, double *chi2, const double *chi2t, double *lam,
+                            hipStream_t st);
+hipError_t launch_fill_cols(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                            double *out, double value, hipStream_t st);
+hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k, double *dst,
+                         int64_t dld, int64_t stride, hipStream_t st);
+hipError_t launch_pick_best(const double *x, const double *chi2, const int32_t *n, int64_t nprob,
+                            int64_t ld, int64_t stride, double *best, double *best_chi2,
+                            hipStream_t st);
+
 }  // namespace iodk
