@@ -107,6 +107,69 @@ def cpu_baseline(wl, obs, target_s):
                       f"{el:.1f} s wall"}
 
 
+def batch_with_observations(iod, wl):
+    """Batch whose observed angles are the library's prediction for each
+    problem's true deputy plus the seeded noise."""
+    zeros = [np.zeros((len(t), 2)) for t in wl.t]
+    b0 = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, zeros, [wl.sigma] * wl.P, h=wl.h)
+    pred = iod.iod_batch_predict(b0, wl.truth)
+    iod.iod_batch_destroy(b0)
+    obs = [pred[p] + wl.noise[p] for p in range(wl.P)]
+    print(f"# observations simulated for {wl.P} problems", file=sys.stderr, flush=True)
+    return iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+
+
+def run_refine(args, iod, torch):
+    """Refinement workload: mixed-precision swarm (2,048 particles, 100
+    iterations, FP64 re-evaluation of the top 64) then Gauss-Newton on each
+    problem's 16 best personal bests, against the plain FP64 swarm on the
+    same 4,096 problems; problem solves/s and final position errors."""
+    from paper_2207_13175_amd import workloads as W
+    wl = W.c4(0)
+    if args.iters is not None:
+        wl.n_iter = args.iters
+    b = batch_with_observations(iod, wl)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+              for p in range(wl.P)]
+    cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
+    steps = iod.iod_batch_steps(b)
+    for _ in range(args.warmup):
+        iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16, n_gn=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g, chi2, J = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
+                                                  n_gn=10)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=0)
+    t1 = time.perf_counter()
+    g64, J64, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t1
+    err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
+    e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
+    q = lambda a: [float(np.quantile(a, v)) for v in (0.1, 0.5, 0.9)]
+    ps = int(wl.n_iter) * int(np.sum(wl.m * steps))
+    return {
+        "metric": METRIC, "value": wl.P / elapsed, "unit": "problem solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name + "_mixed_top64_refine16x10", "problems": wl.P,
+                   "particles": int(wl.m.sum()), "iterations": wl.n_iter,
+                   "steps_range": [int(steps.min()), int(steps.max())],
+                   "particle_steps_per_solve": ps,
+                   "particle_steps_per_s": ps / elapsed,
+                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph},
+                   "pos_err_q10_50_90": q(err),
+                   "fp64_swarm": {"problem_solves_per_s": wl.P / t64,
+                                  "pos_err_q10_50_90": q(e64)},
+                   "problems_at_least_as_accurate_as_fp64_swarm": int(np.sum(err <= e64)),
+                   "speedup_vs_fp64_swarm": t64 / elapsed},
+    }
+
+
 def run_batch(args, iod, torch, top_k=0):
     """The uneven batch: every problem solved by its own swarm, one launch per
     iteration for the whole batch, launch configuration from the autotuner.
@@ -117,13 +180,7 @@ def run_batch(args, iod, torch, top_k=0):
     wl = W.c2(0)
     if args.iters is not None:
         wl.n_iter = args.iters
-    obs = []
-    for p in range(wl.P):
-        one = W.Workload("p", wl.mu, wl.h, wl.sigma, wl.chief[p], wl.truth[p], wl.t[p], wl.noise[p],
-                         1, 1)
-        obs.append(observed_angles(iod, torch, one))
-    print(f"# observations simulated for {wl.P} problems", file=sys.stderr, flush=True)
-    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    b = batch_with_observations(iod, wl)
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
               for p in range(wl.P)]
     cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
@@ -212,6 +269,9 @@ def main():
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "c4":
+        print(json.dumps(run_refine(args, iod, torch)), flush=True)
+        return
     if args.workload in ("c2", "c3"):
         top_k = 64 if args.workload == "c3" else 0
         print(json.dumps(run_batch(args, iod, torch, top_k=top_k)), flush=True)

@@ -257,6 +257,13 @@ int64_t iod_batch_steps(const iod_batch *b, int32_t p);
 int iod_batch_set_config(iod_batch *b, const iod_launch_config *cfg);
 int iod_batch_get_config(const iod_batch *b, iod_launch_config *cfg);
 
+/* Predicted (azimuth, elevation) of one state per problem at that problem's
+ * observation times, as iod_predict (used to simulate observations).
+ *   x       host [P][6] initial states
+ *   angles  host [obs_offsets[P]][2], in the batch's observation layout
+ * Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+int iod_batch_predict(iod_batch *b, const double *x, double *angles);
+
 /* Column offsets of a batched swarm: problem p with m[p] >= 0 particles
  * owns columns off[p] .. off[p] + m[p] - 1 of a [6][ld] array, where
  * off[p] = sum over q < p of m[q] rounded up to a multiple of 64.

@@ -105,6 +105,7 @@ _SIGNATURES = {
                                         C.c_void_p, C.c_void_p]),
     "iod_batch_solve_mixed": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
                                         C.c_int32, _D, _D, _D]),
+    "iod_batch_predict": (C.c_int, [C.c_void_p, _D, _D]),
     "iod_grad_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
     "iod_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
@@ -381,6 +382,15 @@ def iod_batch_get_config(batch: Batch) -> iod_launch_config:
     c = iod_launch_config()
     _check(lib().iod_batch_get_config(batch.ptr, C.byref(c)))
     return c
+
+
+def iod_batch_predict(batch: Batch, x):
+    """Predicted angles of one state per problem (x [P, 6]) -> list of [K_p, 2]."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(batch.P, 6)
+    out = np.empty((int(np.sum(batch.K)), 2))
+    _check(lib().iod_batch_predict(batch.ptr, _dp(x), _dp(out)))
+    off = np.concatenate([[0], np.cumsum(batch.K)])
+    return [out[off[p]:off[p + 1]] for p in range(batch.P)]
 
 
 def iod_batch_offsets(batch: Batch, m):

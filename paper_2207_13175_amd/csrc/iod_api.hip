@@ -1208,6 +1208,31 @@ void single_cols(const iod_handle *h, const double *x, int64_t ld, int64_t m, in
 
 extern "C" {
 
+int iod_batch_predict(iod_batch *b, const double *x, double *angles)
+{
+    int rc = check_batch(b);
+    if (rc != IOD_OK) return rc;
+    if (!x || !angles) return fail(IOD_EINVAL, "null host pointer");
+    const int64_t P = b->P;
+    for (int64_t p = 0; p < P; ++p)
+        if (!finite6(x + 6 * p)) return fail(IOD_EINVAL, "problem %lld: non-finite state", (long long)p);
+    const int64_t rows = b->tab_off[P - 1] + b->probs[P - 1].K;
+    std::vector<ProbDesc> descs(P);
+    for (int64_t p = 0; p < P; ++p) descs[p] = desc_of(b->kargs((int32_t)p), b->probs[p].chief, nullptr);
+    DevBuf dd, dx, doff, dout;
+    HIP_TRY(hipMalloc(&dd.p, P * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dx.p, 6 * P * sizeof(double)));
+    HIP_TRY(hipMalloc(&doff.p, P * sizeof(int64_t)));
+    HIP_TRY(hipMalloc(&dout.p, 2 * rows * sizeof(double)));
+    HIP_TRY(hipMemcpy(dd.p, descs.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dx.p, x, 6 * P * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(doff.p, b->tab_off.data(), P * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIP_TRY(launch_predict_batch((const ProbDesc *)dd.p, P, (const double *)dx.p,
+                                 (const int64_t *)doff.p, (double *)dout.p, nullptr));
+    HIP_TRY(hipMemcpy(angles, dout.p, 2 * rows * sizeof(double), hipMemcpyDeviceToHost));
+    return IOD_OK;
+}
+
 int64_t iod_grad_work_len(const iod_handle *h, int64_t ld)
 {
     if (!h) return fail(IOD_EINVAL, "null handle");

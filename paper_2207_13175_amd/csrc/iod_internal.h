@@ -65,6 +65,10 @@ hipError_t launch_propagate(const KArgs &A, const double *x, int64_t ld, int64_t
                             double *states, hipStream_t st);
 hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m,
                           double *angles, hipStream_t st);
+// Angles of xs [nprob][6] at each problem's observations, out [rows][2]
+// (row_off [nprob] first row of each problem).
+hipError_t launch_predict_batch(const ProbDesc *descs, int64_t nprob, const double *xs,
+                                const int64_t *row_off, double *out, hipStream_t st);
 // descs == null: the single problem d0.
 hipError_t launch_chief(const ProbDesc &d0, const ProbDesc *descs, int64_t nprob, hipStream_t st);
 // bs in {64, 128, 256}; grid = workgroups (nslots for a single problem).

@@ -485,6 +485,53 @@ __global__ __launch_bounds__(256) void k_predict(KArgs A, const double *__restri
     walk(A, X, lds, lds_ns, obs);
 }
 
+// Predicted angles of one state per problem (one workgroup per problem),
+// written at the problem's observation rows of out [rows][2].
+struct StoreAnglesRow {
+    double *out;
+    int32_t k;
+    __device__ __forceinline__ void operator()(const double *row, const double S[6])
+    {
+        const double rx = S[0] - row[TAB_RC + 0];
+        const double ry = S[1] - row[TAB_RC + 1];
+        const double rz = S[2] - row[TAB_RC + 2];
+        const double r = sqrt(rx * rx + ry * ry + rz * rz);
+        double az = NAN, el = NAN;
+        if (r != 0.0) {
+            az = atan2(ry / r, rx / r);
+            el = asin(rz / r);
+        }
+        if (threadIdx.x == 0) {
+            out[2 * (int64_t)k] = az;
+            out[2 * (int64_t)k + 1] = el;
+        }
+        ++k;
+    }
+};
+
+__global__ __launch_bounds__(64) void k_predict_batch(const ProbDesc *__restrict__ descs,
+                                                      const double *__restrict__ xs,
+                                                      const int64_t *__restrict__ row_off,
+                                                      double *__restrict__ out)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    const int64_t p = blockIdx.x;
+    const ProbDesc &D = descs[p];
+    double X[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = xs[6 * p + d];
+    StoreAnglesRow obs{out + 2 * row_off[p], 0};
+    walk(D.k, X, lds, lds_ns, obs);
+}
+
+hipError_t launch_predict_batch(const ProbDesc *descs, int64_t nprob, const double *xs,
+                                const int64_t *row_off, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_predict_batch, dim3((unsigned)nprob), dim3(64), 0, st, descs, xs, row_off, out);
+    return hipGetLastError();
+}
+
 // One workgroup per problem; the chief is propagated with the particle
 // integrator and schedule (its positions do not enter the propagation).
 template <bool SINGLE>

@@ -185,3 +185,14 @@ def c2(seed: int = 0, P: int = 1024, n_iter: int = 150, m_range=(512, 8192),
         m[p] = int(round(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
     return BatchWorkload(f"c2_P{P}_N{n_iter}", MU_EARTH_MOON, h, sigma, chief, truth, ts, noise,
                          m, n_iter, chief - 2e-3, chief + 2e-3, pso_seed=seed)
+
+
+def c4(seed: int = 0, P: int = 4096, n_iter: int = 100, m: int = 2048) -> BatchWorkload:
+    """Refinement workload: 4,096 problems drawn as the uneven batch but with
+    K ~ U{10..60}, arcs T ~ U(0.5, 2.5) and 2,048 particles each, 100
+    iterations; each problem's best personal bests are then refined."""
+    wl = c2(seed + 1000, P=P, n_iter=n_iter, m_range=(m, m), K_range=(10, 60),
+            T_range=(0.5, 2.5))
+    wl.name = f"c4_P{P}_m{m}_N{n_iter}"
+    wl.m = np.full(P, m, dtype=np.int64)
+    return wl
