@@ -3,8 +3,11 @@
 TEST INFRASTRUCTURE. A plain FP64 CPU implementation (``orc.c``) of what the
 GPU library computes, written from the paper (Zuehlke et al., AAS 22-770,
 arXiv 2207.13175): the CR3BP equations of motion (eqs. cr3bp:x-z), classical
-fixed-step RK4, the azimuth/elevation model and weighted residual cost
-(eqs. rel:pos, meas:function, b:total, total:cost) and Algorithm 1 (PSO).
+fixed-step RK4, the range/azimuth/elevation model and weighted residual cost
+(eqs. rel:pos, meas:function, b:total, total:cost), Algorithm 1 (PSO) with
+the constriction factor (eq. constriction:factor), the grid-like
+initialisation and Algorithm 2's stopping rule, and the forward
+sensitivities used to check the GPU adjoint and refinement.
 
 Only ``tests/``, the smoke check and the CPU-baseline leg of the benchmark may
 import this package. The GPU library never imports, links or calls it, and it
@@ -42,13 +45,19 @@ class _Problem(C.Structure):
     _fields_ = [("mu", C.c_double), ("h", C.c_double), ("sigma", C.c_double),
                 ("n_obs", C.c_int32), ("cost_mode", C.c_int32),
                 ("chief", C.c_double * 6),
-                ("t", C.POINTER(C.c_double)), ("angles", C.POINTER(C.c_double))]
+                ("t", C.POINTER(C.c_double)), ("angles", C.POINTER(C.c_double)),
+                ("ranges", C.POINTER(C.c_double)), ("sigma_range", C.c_double)]
 
 
 class _Pso(C.Structure):
     _fields_ = [("omega", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double),
                 ("seed", C.c_uint64), ("problem", C.c_uint64),
-                ("lo", C.c_double * 6), ("hi", C.c_double * 6)]
+                ("lo", C.c_double * 6), ("hi", C.c_double * 6),
+                ("flags", C.c_uint32), ("tol_lag", C.c_int32), ("tol", C.c_double)]
+
+PSO_CONSTRICTION = 1
+PSO_PER_DIM_R = 2
+PSO_GRID_INIT = 4
 
 
 _lib = None
@@ -73,6 +82,19 @@ def _load():
     lib.orc_los_angles.argtypes = [_D, _D, _D]
     lib.orc_predict.argtypes = [C.POINTER(_Problem), _D, _D]
     lib.orc_predict.restype = C.c_int
+    lib.orc_predict_ranges.argtypes = [C.POINTER(_Problem), _D, _D]
+    lib.orc_predict_ranges.restype = C.c_int
+    lib.orc_constriction.argtypes = [C.c_double, C.c_double]
+    lib.orc_constriction.restype = C.c_double
+    lib.orc_grid_levels.argtypes = [C.c_int64, _I64]
+    lib.orc_grid_levels.restype = C.c_int64
+    lib.orc_tolerance_met.argtypes = [C.c_double, C.c_double, C.c_double]
+    lib.orc_tolerance_met.restype = C.c_int
+    lib.orc_pso_solve.argtypes = [C.POINTER(_Problem), C.POINTER(_Pso), C.c_int64, C.c_int64,
+                                  _D, _D, _D, _D, _D, _D, _D, _I64, _D, _I64]
+    lib.orc_pso_solve.restype = C.c_int
+    lib.orc_residuals_per_obs.argtypes = [C.POINTER(_Problem)]
+    lib.orc_residuals_per_obs.restype = C.c_int
     lib.orc_cost.argtypes = [C.POINTER(_Problem), C.c_int64, _D, _D]
     lib.orc_cost.restype = C.c_int
     lib.orc_philox4x64.argtypes = [_U64, _U64, _U64]
@@ -105,33 +127,57 @@ def _f64(a, shape=None):
 
 
 class Problem:
-    """One IOD problem: dynamics, chief state, observation times and angles."""
+    """One IOD problem: dynamics, chief state, observation times and angles,
+    and optionally observed ranges [K] with their noise level sigma_range."""
 
-    def __init__(self, mu, h, sigma, chief, t, angles, cost_mode=COST_PAPER):
+    def __init__(self, mu, h, sigma, chief, t, angles, cost_mode=COST_PAPER, ranges=None,
+                 sigma_range=0.0):
         self.t = _f64(t).ravel()
         self.angles = _f64(angles, (len(self.t), 2))
         self.chief = _f64(chief).ravel()
         self.mu, self.h, self.sigma, self.cost_mode = float(mu), float(h), float(sigma), int(cost_mode)
+        self.ranges = None if ranges is None else _f64(ranges).ravel()
+        if self.ranges is not None and len(self.ranges) != len(self.t):
+            raise ValueError("one range per observation")
+        self.sigma_range = float(sigma_range)
         self._s = _Problem(self.mu, self.h, self.sigma, len(self.t), self.cost_mode,
-                           (C.c_double * 6)(*self.chief), _dp(self.t), _dp(self.angles))
+                           (C.c_double * 6)(*self.chief), _dp(self.t), _dp(self.angles),
+                           _dp(self.ranges) if self.ranges is not None else None,
+                           self.sigma_range)
 
     @property
     def K(self):
         return len(self.t)
 
+    @property
+    def R(self):
+        """Residuals per observation: 3 with ranges, else 2."""
+        return 3 if self.ranges is not None else 2
+
     def with_angles(self, angles):
-        return Problem(self.mu, self.h, self.sigma, self.chief, self.t, angles, self.cost_mode)
+        return Problem(self.mu, self.h, self.sigma, self.chief, self.t, angles, self.cost_mode,
+                       self.ranges, self.sigma_range)
+
+    def with_ranges(self, ranges, sigma_range):
+        return Problem(self.mu, self.h, self.sigma, self.chief, self.t, self.angles,
+                       self.cost_mode, ranges, sigma_range)
+
+    def with_mode(self, cost_mode):
+        return Problem(self.mu, self.h, self.sigma, self.chief, self.t, self.angles, cost_mode,
+                       self.ranges, self.sigma_range)
 
 
 class Pso:
     """Algorithm 1 hyper-parameters, Philox identity and initialisation box."""
 
-    def __init__(self, omega, eta1, eta2, seed, lo, hi, problem=0):
+    def __init__(self, omega, eta1, eta2, seed, lo, hi, problem=0, flags=0, tol=0.0, tol_lag=10):
         self.omega, self.eta1, self.eta2 = float(omega), float(eta1), float(eta2)
         self.seed, self.problem = int(seed), int(problem)
         self.lo, self.hi = _f64(lo).ravel(), _f64(hi).ravel()
+        self.flags, self.tol, self.tol_lag = int(flags), float(tol), int(tol_lag)
         self._s = _Pso(self.omega, self.eta1, self.eta2, self.seed, self.problem,
-                       (C.c_double * 6)(*self.lo), (C.c_double * 6)(*self.hi))
+                       (C.c_double * 6)(*self.lo), (C.c_double * 6)(*self.hi),
+                       self.flags, self.tol_lag, self.tol)
 
 
 def num_threads() -> int:
@@ -192,6 +238,33 @@ def predict(problem: Problem, x0):
     if lib.orc_predict(C.byref(problem._s), _dp(x0), _dp(out)) != 0:
         raise ValueError("invalid problem")
     return out
+
+
+def predict_ranges(problem: Problem, x0):
+    """Predicted ranges |rho| [K] of a deputy starting at x0."""
+    lib = _load()
+    x0 = _f64(x0).ravel()
+    out = np.empty(problem.K)
+    if lib.orc_predict_ranges(C.byref(problem._s), _dp(x0), _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return out
+
+
+def constriction(eta1, eta2):
+    """Constriction factor kappa of eq. (constriction:factor); NaN for phi <= 4."""
+    return _load().orc_constriction(float(eta1), float(eta2))
+
+
+def grid_levels(m):
+    """(levels per dimension [6], grid points G) of the grid initialisation."""
+    n = np.zeros(6, dtype=np.int64)
+    G = _load().orc_grid_levels(int(m), n.ctypes.data_as(_I64))
+    return n, int(G)
+
+
+def tolerance_met(jn, jl, tau):
+    """Algorithm 2's test K = |(jn - jl) / jn| < tau (equal costs give K = 0)."""
+    return bool(_load().orc_tolerance_met(float(jn), float(jl), float(tau)))
 
 
 def cost(problem: Problem, x):
@@ -263,13 +336,23 @@ def pso_iterate(problem: Problem, pso: Pso, s: SwarmState, n_count: int):
     return hist[:n_count]
 
 
-def pso_solve(problem: Problem, pso: Pso, m: int, n_iter: int):
-    """Full Algorithm 1 run: (best state, best cost, history [n_iter + 1], swarm).
-    history[0] is the global-best cost after initialisation."""
-    s = pso_init(problem, pso, m)
-    h0 = s.jg.value
-    hist = pso_iterate(problem, pso, s, n_iter)
-    return s.g.copy(), s.jg.value, np.concatenate([[h0], hist]), s
+def pso_solve(problem: Problem, pso: Pso, m: int, n_iter: int, with_n_run=False):
+    """Full Algorithm 1 run, ended early by Algorithm 2 when pso.tol > 0:
+    (best state, best cost, history [n_iter + 1], swarm[, iterations run]).
+    history[0] is the global-best cost after initialisation; entries after
+    the last iteration run are NaN."""
+    lib = _load()
+    s = SwarmState(m)
+    hist = np.empty(n_iter + 1)
+    n_run = C.c_int64(0)
+    rc = lib.orc_pso_solve(C.byref(problem._s), C.byref(pso._s), m, n_iter, _dp(s.x), _dp(s.v),
+                           _dp(s.p), _dp(s.jp), _dp(s.cost), _dp(s.g), C.byref(s.jg),
+                           C.byref(s.gi), _dp(hist), C.byref(n_run))
+    if rc != 0:
+        raise ValueError("invalid problem or parameters")
+    s.iter = n_run.value
+    out = (s.g.copy(), s.jg.value, hist, s)
+    return out + (n_run.value,) if with_n_run else out
 
 
 def rhs_jac(mu, s):
@@ -291,12 +374,14 @@ def rk4_step_tangent(mu, h, s, phi):
 
 
 def residuals(problem: Problem, x0, jacobian=False):
-    """Whitened residuals [2K] (azimuth, elevation per observation, divided by
-    sigma) and, if asked, their Jacobian [2K, 6] from the RK4 tangent."""
+    """Whitened residuals [R K] (azimuth, elevation and, with ranges, range per
+    observation, each divided by its sigma) and, if asked, their Jacobian
+    [R K, 6] from the RK4 tangent."""
     lib = _load()
     x0 = _f64(x0).ravel()
-    r = np.empty(2 * problem.K)
-    jac = np.empty((2 * problem.K, 6)) if jacobian else None
+    R = problem.R
+    r = np.empty(R * problem.K)
+    jac = np.empty((R * problem.K, 6)) if jacobian else None
     rc = lib.orc_residuals(C.byref(problem._s), _dp(x0), _dp(r), _dp(jac) if jacobian else None)
     if rc < 0:
         raise ValueError("invalid problem")

@@ -25,9 +25,14 @@
  *     line-of-sight unit vector, azimuth/elevation, measurement function
  *     eq. (meas:function), residual b = y_obs - y, weights w_j = 1/sigma_j^2,
  *     b_total eq. (b:total) and the scalar cost eq. (total:cost).
- *   - Algorithm 1 (particle swarm optimisation).
- * The integrator (classical fixed-step RK4), the angles-only measurement set
- * and the readings of the garbled passages are stated where they are used.
+ *   - Algorithm 1 (particle swarm optimisation), with the constriction factor
+ *     eq. (constriction:factor), the "grid-like" initialisation (Methodology,
+ *     Particle Swarm Optimizer) and Algorithm 2 (tolerance) as its stopping
+ *     rule; all three are options, off by default.
+ *   - The range component of eq. (meas:function), optional (angles only by
+ *     default).
+ * The integrator (classical fixed-step RK4) and the readings of the garbled
+ * passages are stated where they are used.
  *
  * Parity pins: every function here is pinned by the CPU tests (closed-form
  * equilibria, the mu = 0 Kepler circle, h^4 convergence of the Jacobi
@@ -35,7 +40,10 @@
  * constants and period ratios, literal-formula angle residuals in extended
  * precision, noise statistics of the cost, a brute-force grid minimum, the
  * PSO invariants and isolated velocity-update terms, Philox bit patterns
- * from numpy).
+ * from numpy; for the variants: chi-square statistics with ranges, the
+ * published constriction value and its quadratic identity, the Cartesian
+ * cell-centre lattice, and Algorithm 2's stop index recomputed from an
+ * untruncated run).
  */
 #include <math.h>
 #include <omp.h>
@@ -56,6 +64,8 @@ typedef struct {
     double chief[6];      /* chief state at t = 0 */
     const double *t;      /* [K] observation times, t_0 = 0 is the epoch */
     const double *angles; /* [K][2] observed (azimuth, elevation), rad */
+    const double *ranges; /* [K] observed ranges |rho| (LU), or NULL: angles only */
+    double sigma_range;   /* range noise level (LU); weight w_1 = 1/sigma_range^2 */
 } orc_problem;
 
 /* Swarm hyper-parameters of Algorithm 1 plus the random-stream identity. */
@@ -67,7 +77,15 @@ typedef struct {
     uint64_t problem;  /* Philox counter word 2 (problem index in a batch) */
     double lo[6];      /* initialisation box, absolute */
     double hi[6];
+    uint32_t flags;    /* ORC_PSO_* variants; 0 = Algorithm 1 as printed */
+    int32_t tol_lag;   /* Algorithm 2: compare with the global best this many iterations back */
+    double tol;        /* Algorithm 2 tolerance tau; 0 = run every iteration */
 } orc_pso;
+
+/* Variants the paper describes beside Algorithm 1. */
+#define ORC_PSO_CONSTRICTION 1u /* multiply the new velocity by kappa, eq. (constriction:factor) */
+#define ORC_PSO_PER_DIM_R 2u    /* independent r1, r2 for every dimension */
+#define ORC_PSO_GRID_INIT 4u    /* "grid-like" uniform initialisation (Methodology, PSO) */
 
 /* ------------------------------------------------------------------------ */
 /* Dynamics: eqs. (cr3bp:x)-(cr3bp:z).                                       */
@@ -214,9 +232,9 @@ static void chief_positions(const orc_problem *P, const int64_t *ns, const doubl
     free(st);
 }
 
-/* Predicted (azimuth, elevation) of a deputy starting at x0, at every
- * observation time; out is [K][2]. Used to simulate observations. */
-int orc_predict(const orc_problem *P, const double x0[6], double *out)
+/* Relative positions rho_k = r_deputy(t_k) - r_chief(t_k), eq. (rel:pos), of
+ * a deputy starting at x0; rho is [K][3]. */
+static int rel_positions(const orc_problem *P, const double x0[6], double *rho)
 {
     const int32_t K = P->n_obs;
     int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
@@ -224,19 +242,45 @@ int orc_predict(const orc_problem *P, const double x0[6], double *out)
     double *rc = (double *)malloc(sizeof(double) * 3 * (size_t)K);
     double *st = (double *)malloc(sizeof(double) * 6 * (size_t)K);
     int32_t k;
+    int d;
     int rc_ok = orc_schedule(P->t, K, P->h, ns, tau);
     if (rc_ok == 0) {
         chief_positions(P, ns, tau, rc);
         orc_propagate(P->mu, P->h, x0, K, ns, tau, st);
-        for (k = 0; k < K; k++) {
-            double rho[3];
-            rho[0] = st[6 * k + 0] - rc[3 * k + 0];
-            rho[1] = st[6 * k + 1] - rc[3 * k + 1];
-            rho[2] = st[6 * k + 2] - rc[3 * k + 2];
-            orc_los_angles(rho, &out[2 * k], &out[2 * k + 1]);
-        }
+        for (k = 0; k < K; k++)
+            for (d = 0; d < 3; d++) rho[3 * k + d] = st[6 * k + d] - rc[3 * k + d];
     }
     free(ns); free(tau); free(rc); free(st);
+    return rc_ok;
+}
+
+/* Predicted (azimuth, elevation) of a deputy starting at x0, at every
+ * observation time; out is [K][2]. Used to simulate observations. */
+int orc_predict(const orc_problem *P, const double x0[6], double *out)
+{
+    double *rho = (double *)malloc(sizeof(double) * 3 * (size_t)P->n_obs);
+    int32_t k;
+    int rc_ok = rel_positions(P, x0, rho);
+    if (rc_ok == 0)
+        for (k = 0; k < P->n_obs; k++) orc_los_angles(rho + 3 * k, &out[2 * k], &out[2 * k + 1]);
+    free(rho);
+    return rc_ok;
+}
+
+/* Predicted ranges rho(t_k) = |rho(t_k)| (the range entry of eq.
+ * (meas:function)) of a deputy starting at x0; out is [K]. Used to simulate
+ * range measurements. */
+int orc_predict_ranges(const orc_problem *P, const double x0[6], double *out)
+{
+    double *rho = (double *)malloc(sizeof(double) * 3 * (size_t)P->n_obs);
+    int32_t k;
+    int rc_ok = rel_positions(P, x0, rho);
+    if (rc_ok == 0)
+        for (k = 0; k < P->n_obs; k++) {
+            const double *r = rho + 3 * k;
+            out[k] = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        }
+    free(rho);
     return rc_ok;
 }
 
@@ -274,7 +318,9 @@ static int residual(const double rho[3], double sa, double ca, double sb, double
 typedef struct {
     int64_t *ns;
     double *tau, *rc, *sa, *ca, *sb, *cb;
-    double w;
+    double w;              /* angle weight 1/sigma^2 */
+    double wr;             /* range weight 1/sigma_range^2 (ranges only) */
+    const double *ranges;  /* observed ranges or NULL */
 } tables;
 
 static int tables_make(const orc_problem *P, tables *T)
@@ -298,6 +344,8 @@ static int tables_make(const orc_problem *P, tables *T)
     }
     /* weights w_j = 1/sigma_j^2 with one sigma for both angles */
     T->w = 1.0 / (P->sigma * P->sigma);
+    T->ranges = P->ranges;
+    T->wr = P->ranges ? 1.0 / (P->sigma_range * P->sigma_range) : 0.0;
     return 0;
 }
 
@@ -307,8 +355,33 @@ static void tables_free(tables *T)
     free(T->sa); free(T->ca); free(T->sb); free(T->cb);
 }
 
+/* Range |rho| of a relative position, the first component of the
+ * measurement function eq. (meas:function), in the fixed evaluation order
+ * sqrt(x^2 + (y^2 + z^2)) with fused products. */
+static double range_of(const double rho[3])
+{
+    return sqrt(fma(rho[0], rho[0], fma(rho[1], rho[1], rho[2] * rho[2])));
+}
+
+/* Weighted squared residual e_k = b_k^T W b_k of one observation, eq.
+ * (b:total): angles only, w (da^2 + db^2); with ranges the measurement
+ * function eq. (meas:function) is (range, azimuth, elevation) and
+ * W = diag(w_1, w, w), so e_k = w_1 dr^2 + w (da^2 + db^2) with
+ * dr = range_obs - |rho|. +inf when rho = 0 (no line of sight). */
+static double obs_error(const tables *T, int32_t k, const double rho[3])
+{
+    double da, db, e;
+    if (residual(rho, T->sa[k], T->ca[k], T->sb[k], T->cb[k], &da, &db) != 0) return INFINITY;
+    e = T->w * fma(da, da, db * db);
+    if (T->ranges) {
+        const double dr = T->ranges[k] - range_of(rho);
+        e = fma(T->wr * dr, dr, e);
+    }
+    return e;
+}
+
 /* Cost J of one particle, eqs. (b:total) and (total:cost): per observation
- * e_k = b_k^T W b_k = w (da^2 + db^2); b_total = [e_1 ... e_K] is a row
+ * e_k = b_k^T W b_k (obs_error); b_total = [e_1 ... e_K] is a row
  * vector and "the square of the row vector" is read as its inner product,
  * J = sum_k e_k^2 (PAPER mode). CHI2 mode is J = sum_k e_k. Accumulated in
  * ascending k from +0. A zero line of sight makes e_k = +inf. */
@@ -320,7 +393,7 @@ static double cost_one(const orc_problem *P, const tables *T, const double x0[6]
     int32_t k;
     memcpy(X, x0, sizeof X);
     for (k = 0; k < P->n_obs; k++) {
-        double S[6], rho[3], da, db, e;
+        double S[6], rho[3], e;
         while (step < T->ns[k]) {
             orc_rk4_step(P->mu, P->h, X);
             step++;
@@ -330,10 +403,7 @@ static double cost_one(const orc_problem *P, const tables *T, const double x0[6]
         rho[0] = S[0] - T->rc[3 * k + 0];
         rho[1] = S[1] - T->rc[3 * k + 1];
         rho[2] = S[2] - T->rc[3 * k + 2];
-        if (residual(rho, T->sa[k], T->ca[k], T->sb[k], T->cb[k], &da, &db) != 0)
-            e = INFINITY;
-        else
-            e = T->w * fma(da, da, db * db);
+        e = obs_error(T, k, rho);
         if (P->cost_mode == ORC_COST_CHI2)
             J = J + e;
         else
@@ -423,28 +493,82 @@ static int64_t argmin(int64_t m, const double *jp)
     return best;
 }
 
+/* Constriction factor, eq. (constriction:factor):
+ * kappa = 2 / |2 - phi - sqrt(phi^2 - 4 phi)|, phi = eta1 + eta2, defined for
+ * phi > 4 (NaN otherwise). */
+double orc_constriction(double eta1, double eta2)
+{
+    const double phi = eta1 + eta2;
+    if (!(phi > 4.0)) return NAN;
+    return 2.0 / fabs(2.0 - phi - sqrt(phi * phi - 4.0 * phi));
+}
+
+/* Levels per dimension of the "grid-like" initialisation (Methodology,
+ * Particle Swarm Optimizer) for m particles: a Cartesian grid as even as m
+ * allows. Every dimension gets b levels, b the largest integer with
+ * b^6 <= m; then dimensions 0, 1, ... in turn get b + 1 levels while the
+ * product stays <= m. Returns the number of grid points G = prod n[d]. */
+int64_t orc_grid_levels(int64_t m, int64_t n[6])
+{
+    int64_t b = 1, G;
+    int d;
+    if (m < 1) return 0;
+    for (;;) {
+        const int64_t c = b + 1;
+        if (c * c * c * c * c * c > m) break;
+        b = c;
+    }
+    G = 1;
+    for (d = 0; d < 6; d++) {
+        n[d] = b;
+        G *= b;
+    }
+    for (d = 0; d < 6; d++) {
+        if (G / b * (b + 1) > m) break;
+        G = G / b * (b + 1);
+        n[d] = b + 1;
+    }
+    return G;
+}
+
 /* Algorithm 1, initialisation: particle states uniform in the box
  * (x = lo + (hi - lo) u, u from Philox counter (b, i, problem, 0) where block
  * b = 0 gives dimensions 0-3 and b = 1 dimensions 4-5), velocities zero,
  * personal bests equal to the initial states, global best the lowest-cost
- * particle. Arrays are [m][6] (x, v, p) and [m] (jp, cost). g receives the
+ * particle. With ORC_PSO_GRID_INIT the first G = prod n[d] particles
+ * (orc_grid_levels) instead sit on the cell centres of the grid over the
+ * box: particle i has mixed-radix digits j_d (dimension 0 varying fastest)
+ * and u_d = (2 j_d + 1) / (2 n_d); the remaining m - G particles are drawn
+ * as above. Arrays are [m][6] (x, v, p) and [m] (jp, cost). g receives the
  * global-best state, *jg its cost key and *gi the particle index. */
 int orc_pso_init(const orc_problem *P, const orc_pso *S, int64_t m,
                  double *x, double *v, double *p, double *jp, double *cost,
                  double g[6], double *jg, int64_t *gi)
 {
     const uint64_t key2[2] = {S->seed, 0};
-    int64_t i;
+    int64_t i, n[6], G = 0;
     int d;
     if (m < 1) return -1;
+    if (S->flags & ORC_PSO_GRID_INIT) G = orc_grid_levels(m, n);
     for (i = 0; i < m; i++) {
-        uint64_t c[4], u[8];
-        c[0] = 0; c[1] = (uint64_t)i; c[2] = S->problem; c[3] = 0;
-        orc_philox4x64(c, key2, u);
-        c[0] = 1;
-        orc_philox4x64(c, key2, u + 4);
+        double u[6];
+        if (i < G) {
+            int64_t j = i;
+            for (d = 0; d < 6; d++) {
+                const int64_t jd = j % n[d];
+                j /= n[d];
+                u[d] = (double)(2 * jd + 1) / (double)(2 * n[d]);
+            }
+        } else {
+            uint64_t c[4], w[8];
+            c[0] = 0; c[1] = (uint64_t)i; c[2] = S->problem; c[3] = 0;
+            orc_philox4x64(c, key2, w);
+            c[0] = 1;
+            orc_philox4x64(c, key2, w + 4);
+            for (d = 0; d < 6; d++) u[d] = u01(w[d]);
+        }
         for (d = 0; d < 6; d++) {
-            x[6 * i + d] = S->lo[d] + (S->hi[d] - S->lo[d]) * u01(u[d]);
+            x[6 * i + d] = S->lo[d] + (S->hi[d] - S->lo[d]) * u[d];
             v[6 * i + d] = 0.0;
         }
     }
@@ -462,39 +586,63 @@ int orc_pso_init(const orc_problem *P, const orc_pso *S, int64_t m,
 /* Algorithm 1, iterations n = n_first .. n_first + n_count - 1 (n counts from
  * 1). For each particle: evaluate the current state (at n = 1 the
  * initialisation's cost of the same state is reused), keep it as the personal
- * best if strictly lower (NaN ranks as +inf), draw r1, r2 (Philox counter (n, i, problem, 1),
- * words 0 and 1), then
+ * best if strictly lower (NaN ranks as +inf), draw r1, r2 (Philox counter
+ * (n, i, problem, 1), words 0 and 1), then
  *   v <- omega v + eta1 r1 (p - x) + eta2 r2 (g - x),   x <- x + v,
- * using the global best g of the previous iteration. After the whole swarm:
- * if the lowest personal-best cost is strictly below the global-best cost,
- * the global best moves to that personal best. hist (may be NULL) receives
- * the global-best cost after each iteration. */
+ * using the global best g of the previous iteration. With
+ * ORC_PSO_PER_DIM_R every dimension d has its own r1_d, r2_d: words 2d and
+ * 2d + 1 of the twelve from counters (n, i, problem, 2), (.., 3), (.., 4).
+ * With ORC_PSO_CONSTRICTION the new velocity is multiplied by kappa
+ * (orc_constriction). After the whole swarm: if the lowest personal-best
+ * cost is strictly below the global-best cost, the global best moves to that
+ * personal best. hist (may be NULL) receives the global-best cost after each
+ * iteration. */
 int orc_pso_iterate(const orc_problem *P, const orc_pso *S, int64_t m,
                     int64_t n_first, int64_t n_count,
                     double *x, double *v, double *p, double *jp, double *cost,
                     double g[6], double *jg, int64_t *gi, double *hist)
 {
     const uint64_t key2[2] = {S->seed, 0};
+    const int constrict = (S->flags & ORC_PSO_CONSTRICTION) != 0;
+    const int per_dim = (S->flags & ORC_PSO_PER_DIM_R) != 0;
+    const double kappa = constrict ? orc_constriction(S->eta1, S->eta2) : 1.0;
     int64_t n, i;
     int d;
     if (m < 1 || n_first < 1 || n_count < 0) return -1;
+    if (constrict && isnan(kappa)) return -1;
     for (n = n_first; n < n_first + n_count; n++) {
         int64_t b;
         if (n >= 2 && orc_cost(P, m, x, cost) != 0) return -1;
         for (i = 0; i < m; i++) {
-            uint64_t c[4], u[4];
-            double a1, a2;
+            uint64_t c[4], u[12];
+            double a1[6], a2[6];
             if (key(cost[i]) < key(jp[i])) {
                 jp[i] = cost[i];
                 for (d = 0; d < 6; d++) p[6 * i + d] = x[6 * i + d];
             }
-            c[0] = (uint64_t)n; c[1] = (uint64_t)i; c[2] = S->problem; c[3] = 1;
-            orc_philox4x64(c, key2, u);
-            a1 = S->eta1 * u01(u[0]);
-            a2 = S->eta2 * u01(u[1]);
+            c[0] = (uint64_t)n; c[1] = (uint64_t)i; c[2] = S->problem;
+            if (per_dim) {
+                int blk;
+                for (blk = 0; blk < 3; blk++) {
+                    c[3] = 2 + (uint64_t)blk;
+                    orc_philox4x64(c, key2, u + 4 * blk);
+                }
+                for (d = 0; d < 6; d++) {
+                    a1[d] = S->eta1 * u01(u[2 * d]);
+                    a2[d] = S->eta2 * u01(u[2 * d + 1]);
+                }
+            } else {
+                c[3] = 1;
+                orc_philox4x64(c, key2, u);
+                for (d = 0; d < 6; d++) {
+                    a1[d] = S->eta1 * u01(u[0]);
+                    a2[d] = S->eta2 * u01(u[1]);
+                }
+            }
             for (d = 0; d < 6; d++) {
                 double xi = x[6 * i + d];
-                double vi = S->omega * v[6 * i + d] + a1 * (p[6 * i + d] - xi) + a2 * (g[d] - xi);
+                double vi = S->omega * v[6 * i + d] + a1[d] * (p[6 * i + d] - xi) + a2[d] * (g[d] - xi);
+                if (constrict) vi = kappa * vi;
                 v[6 * i + d] = vi;
                 x[6 * i + d] = xi + vi;
             }
@@ -507,6 +655,42 @@ int orc_pso_iterate(const orc_problem *P, const orc_pso *S, int64_t m,
         }
         if (hist) hist[n - n_first] = *jg;
     }
+    return 0;
+}
+
+/* Algorithm 2's test after iteration n > L: with the global best matrix
+ * J_g,0..n, K = |(J_g,n - J_g,n-L) / J_g,n| < tau ends the run. Equal costs
+ * count as K = 0, so a run stuck at J_g = 0 (or with no finite cost yet)
+ * also ends rather than dividing 0 by 0. */
+int orc_tolerance_met(double jn, double jl, double tau)
+{
+    const double K = (jn == jl) ? 0.0 : fabs((jn - jl) / jn);
+    return K < tau;
+}
+
+/* Algorithm 1 from initialisation to the end, with Algorithm 2 as its
+ * stopping rule when S->tol > 0 (lag L = S->tol_lag >= 1): after iteration
+ * n > L the run ends if orc_tolerance_met(J_g,n, J_g,n-L, tol). hist is
+ * [n_iter + 1]: hist[0] after initialisation, hist[n] after iteration n,
+ * NaN after the last iteration run; *n_run receives that iteration. */
+int orc_pso_solve(const orc_problem *P, const orc_pso *S, int64_t m, int64_t n_iter,
+                  double *x, double *v, double *p, double *jp, double *cost,
+                  double g[6], double *jg, int64_t *gi, double *hist, int64_t *n_run)
+{
+    int64_t n;
+    if (n_iter < 0 || !(S->tol >= 0.0) || (S->tol > 0.0 && S->tol_lag < 1)) return -1;
+    if (orc_pso_init(P, S, m, x, v, p, jp, cost, g, jg, gi) != 0) return -1;
+    hist[0] = *jg;
+    *n_run = 0;
+    for (n = 1; n <= n_iter; n++) {
+        if (orc_pso_iterate(P, S, m, n, 1, x, v, p, jp, cost, g, jg, gi, hist + n) != 0)
+            return -1;
+        *n_run = n;
+        if (S->tol > 0.0 && n > S->tol_lag &&
+            orc_tolerance_met(hist[n], hist[n - S->tol_lag], S->tol))
+            break;
+    }
+    for (n = *n_run + 1; n <= n_iter; n++) hist[n] = NAN;
     return 0;
 }
 
@@ -605,10 +789,20 @@ static void residual_grad(const double rho[3], double ga[3], double gb[3])
     gb[2] = -rxy / r2;
 }
 
-/* Whitened residuals r[2k] = da_k / sigma, r[2k+1] = db_k / sigma at x0 and,
- * if jac is not NULL, their Jacobian jac[2K][6] with respect to x0 through
- * the discrete RK4 tangent. Returns 0, -1 on an invalid schedule, 1 if some
- * line of sight vanishes (residuals there are NaN). */
+/* Residuals per observation: 3 with ranges (range, azimuth, elevation), else
+ * 2 (azimuth, elevation). */
+int orc_residuals_per_obs(const orc_problem *P)
+{
+    return P->ranges ? 3 : 2;
+}
+
+/* Whitened residuals at x0, R = orc_residuals_per_obs(P) per observation:
+ * r[R k] = da_k / sigma, r[R k + 1] = db_k / sigma and, with ranges,
+ * r[R k + 2] = dr_k / sigma_range (so that sum r^2 = sum_k e_k), and, if jac
+ * is not NULL, their Jacobian jac[R K][6] with respect to x0 through the
+ * discrete RK4 tangent (d|rho|/d rho = rho / |rho|). Returns 0, -1 on an
+ * invalid schedule, 1 if some line of sight vanishes (residuals there are
+ * NaN). */
 int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *jac)
 {
     tables T;
@@ -616,7 +810,9 @@ int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *j
     int64_t step = 0;
     int32_t k;
     int i, d, bad = 0;
+    const int R = orc_residuals_per_obs(P);
     const double is = 1.0 / P->sigma;
+    const double isr = P->ranges ? 1.0 / P->sigma_range : 0.0;
     if (tables_make(P, &T) != 0) {
         tables_free(&T);
         return -1;
@@ -624,7 +820,7 @@ int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *j
     memcpy(X, x0, sizeof X);
     for (i = 0; i < 36; i++) Phi[i] = (i % 7 == 0) ? 1.0 : 0.0;
     for (k = 0; k < P->n_obs; k++) {
-        double S[6], SP[36], rho[3], da, db;
+        double S[6], SP[36], rho[3], da, db, rr = 0.0;
         while (step < T.ns[k]) {
             if (jac)
                 orc_rk4_step_tangent(P->mu, P->h, X, Phi);
@@ -646,19 +842,25 @@ int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *j
             db = NAN;
             bad = 1;
         }
-        r[2 * k] = da * is;
-        r[2 * k + 1] = db * is;
+        r[R * k] = da * is;
+        r[R * k + 1] = db * is;
+        if (R == 3) {
+            rr = range_of(rho);
+            r[R * k + 2] = (P->ranges[k] - rr) * isr;
+        }
         if (jac) {
             double ga[3], gb[3];
             residual_grad(rho, ga, gb);
             for (i = 0; i < 6; i++) {
-                double ja = 0.0, jb = 0.0;
+                double ja = 0.0, jb = 0.0, jr = 0.0;
                 for (d = 0; d < 3; d++) {
                     ja += ga[d] * SP[6 * d + i];
                     jb += gb[d] * SP[6 * d + i];
+                    if (R == 3) jr -= rho[d] / rr * SP[6 * d + i];
                 }
-                jac[6 * (2 * k) + i] = ja * is;
-                jac[6 * (2 * k + 1) + i] = jb * is;
+                jac[6 * (R * k) + i] = ja * is;
+                jac[6 * (R * k + 1) + i] = jb * is;
+                if (R == 3) jac[6 * (R * k + 2) + i] = jr * isr;
             }
         }
     }
@@ -667,25 +869,31 @@ int orc_residuals(const orc_problem *P, const double x0[6], double *r, double *j
 }
 
 /* Gradient of the cost J at x0 from the forward sensitivities: with
- * e_k = r_a^2 + r_b^2 (whitened residuals), dJ/dx0 = sum_k g'(e_k) de_k/dx0,
- * de_k = 2 (r_a dr_a + r_b dr_b), g'(e) = 2e (sum e_k^2) or 1 (sum e_k).
- * Writes grad[6] and *J; returns as orc_residuals. */
+ * e_k = sum of the observation's squared whitened residuals,
+ * dJ/dx0 = sum_k g'(e_k) de_k/dx0, de_k = 2 sum_j r_j dr_j,
+ * g'(e) = 2e (sum e_k^2) or 1 (sum e_k). Writes grad[6] and *J; returns as
+ * orc_residuals. */
 int orc_grad(const orc_problem *P, const double x0[6], double grad[6], double *J)
 {
     const int32_t K = P->n_obs;
-    double *r = (double *)malloc(sizeof(double) * 2 * (size_t)K);
-    double *jac = (double *)malloc(sizeof(double) * 12 * (size_t)K);
+    const int R = orc_residuals_per_obs(P);
+    double *r = (double *)malloc(sizeof(double) * (size_t)R * (size_t)K);
+    double *jac = (double *)malloc(sizeof(double) * 6 * (size_t)R * (size_t)K);
     int32_t k;
-    int i;
+    int i, j;
     int rc = orc_residuals(P, x0, r, jac);
     double acc = 0.0;
     for (i = 0; i < 6; i++) grad[i] = 0.0;
     for (k = 0; k < K; k++) {
-        const double e = r[2 * k] * r[2 * k] + r[2 * k + 1] * r[2 * k + 1];
-        const double gp = P->cost_mode == ORC_COST_CHI2 ? 1.0 : 2.0 * e;
+        double e = 0.0, gp;
+        for (j = 0; j < R; j++) e += r[R * k + j] * r[R * k + j];
+        gp = P->cost_mode == ORC_COST_CHI2 ? 1.0 : 2.0 * e;
         acc += P->cost_mode == ORC_COST_CHI2 ? e : e * e;
-        for (i = 0; i < 6; i++)
-            grad[i] += gp * 2.0 * (r[2 * k] * jac[6 * (2 * k) + i] + r[2 * k + 1] * jac[6 * (2 * k + 1) + i]);
+        for (i = 0; i < 6; i++) {
+            double de = 0.0;
+            for (j = 0; j < R; j++) de += r[R * k + j] * jac[6 * (R * k + j) + i];
+            grad[i] += gp * 2.0 * de;
+        }
     }
     *J = acc;
     free(r);
