@@ -63,7 +63,8 @@ typedef struct {
     int32_t reserved;  /* must be 0 */
 } iod_options;
 
-/* Algorithm 1 hyper-parameters and the random-stream identity. */
+/* Algorithm 1 hyper-parameters, the random-stream identity and the paper's
+ * optional variants. All-zero variant fields give Algorithm 1 as printed. */
 typedef struct {
     double omega;     /* inertia weight */
     double eta1;      /* cognitive weight (pull to the personal best) */
@@ -72,7 +73,34 @@ typedef struct {
     uint64_t problem; /* Philox counter word 2; 0 for a single problem */
     double lo[6];     /* initialisation box, absolute, lo[d] <= hi[d] */
     double hi[6];
+    uint32_t flags;   /* IOD_PSO_* bits, 0 = none */
+    int32_t tol_lag;  /* Algorithm 2 lag L >= 1 (the paper's listing uses 10); read when tol > 0 */
+    double tol;       /* Algorithm 2 tolerance tau >= 0; 0 = run every iteration */
 } iod_pso_params;
+
+/* Constriction factor (eq. constriction:factor): the new velocity is
+ * multiplied by kappa = 2 / |2 - phi - sqrt(phi^2 - 4 phi)|, phi = eta1 + eta2,
+ * which must exceed 4. omega is kept (omega = 1 gives the classical
+ * constricted swarm). */
+#define IOD_PSO_CONSTRICTION 1u
+/* Independent r1, r2 per dimension: words 2d and 2d + 1 of Philox counters
+ * (n, i, problem, 2), (n, i, problem, 3), (n, i, problem, 4). */
+#define IOD_PSO_PER_DIM_R 2u
+/* "Grid-like" initialisation (Methodology, Particle Swarm Optimizer): the
+ * first G particles sit on the cell centres of a Cartesian grid over the box
+ * with n_d levels per dimension (every dimension b levels, b the largest
+ * integer with b^6 <= m, then dimensions 0, 1, ... raised to b + 1 while the
+ * product G stays <= m); particle i has mixed-radix digits j_d, dimension 0
+ * fastest, and x_d = lo_d + (hi_d - lo_d) (2 j_d + 1) / (2 n_d). The other
+ * m - G particles are drawn as without the flag. */
+#define IOD_PSO_GRID_INIT 4u
+
+/* Algorithm 2 (tolerance): with tol > 0, after iteration n > L the run of a
+ * problem ends if K = |(J_g,n - J_g,n-L) / J_g,n| < tol, J_g,n the global-best
+ * cost after iteration n (equal costs count as K = 0). Its global best is
+ * then final; later iterations leave its swarm unchanged and write NaN into
+ * its history, so the last finite history entry marks the iteration at
+ * which it stopped. */
 
 /* Launch configuration of the swarm kernels (see iod_set_config,
  * iod_batch_set_config, iod_batch_autotune). Results do not depend on it. */
@@ -143,6 +171,17 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
                const double *obs_angles, int32_t n_obs, double sigma,
                const iod_options *opt, iod_handle **out);
 
+/* As iod_create, with range measurements as well (the range entry of eq.
+ * meas:function): obs_ranges host [n_obs] observed |rho| (LU, finite, >= 0),
+ * sigma_range > 0 their noise level, weight 1/sigma_range^2. Every cost,
+ * gradient and refinement of the handle then uses
+ * e_k = (range_obs - |rho|)^2 / sigma_range^2 + (b_az^2 + b_el^2) / sigma^2.
+ * obs_ranges = NULL gives iod_create (sigma_range is then ignored). */
+int iod_create_ranged(double mu, const double chief_state[6], const double *obs_times,
+                      const double *obs_angles, const double *obs_ranges, int32_t n_obs,
+                      double sigma, double sigma_range, const iod_options *opt,
+                      iod_handle **out);
+
 /* Release a handle and its device tables (NULL is accepted). Synchronises
  * the device before freeing. */
 int iod_destroy(iod_handle *h);
@@ -175,24 +214,33 @@ int iod_propagate(iod_handle *h, const double *x, int64_t ld, int64_t m,
 int iod_predict(iod_handle *h, const double *x, int64_t ld, int64_t m,
                 double *angles, void *stream);
 
+/* Predicted ranges |rho| (the range entry of eq. meas:function) of each
+ * particle at every observation time: ranges device [K][ld],
+ * ranges[k * ld + i]. Errors: IOD_EINVAL, IOD_EDEVICE. */
+int iod_predict_ranges(iod_handle *h, const double *x, int64_t ld, int64_t m,
+                       double *ranges, void *stream);
+
 /* Swarm fitness (eqs. b:total, total:cost): for each particle the residuals
  * b_k = observed - predicted (azimuth wrapped to (-pi, pi]),
- * e_k = (b_az^2 + b_el^2) / sigma^2 and J = sum_k e_k^2 (IOD_COST_PAPER) or
- * sum_k e_k (IOD_COST_CHI2).
+ * e_k = (b_az^2 + b_el^2) / sigma^2 (plus the range term for a handle made by
+ * iod_create_ranged) and J = sum_k e_k^2 (IOD_COST_PAPER) or sum_k e_k
+ * (IOD_COST_CHI2).
  *   x    device [6][ld];  cost device [ld] (first m written)
  * Errors: IOD_EINVAL, IOD_EDEVICE. */
 int iod_eval_swarm(iod_handle *h, const double *x, int64_t ld, int64_t m,
                    double *cost, void *stream);
 
 /* Doubles needed in iod_swarm.work for a swarm of m particles (>= 1) under
- * any launch configuration, or a negative code. */
+ * any launch configuration (argmin slots, global-best records and the
+ * Algorithm 2 state), or a negative code. */
 int64_t iod_swarm_work_len(int64_t m);
 
 /* Algorithm 1 initialisation: x uniform in [lo, hi] from Philox4x64-10
  * (counter (b, i, problem, 0), b = 0 for dimensions 0-3 and 1 for 4-5,
- * u = (word >> 11) 2^-53, x = lo + (hi - lo) u), v = 0, one evaluation,
- * p = x, jp = cost, global best = lowest-cost particle. Sets s->iter = 0.
- * Errors: IOD_EINVAL, IOD_EDEVICE. */
+ * u = (word >> 11) 2^-53, x = lo + (hi - lo) u), or on the grid with
+ * IOD_PSO_GRID_INIT; v = 0, one evaluation, p = x, jp = cost, global best =
+ * lowest-cost particle. Sets s->iter = 0.
+ * Errors: IOD_EINVAL (also for invalid variant fields), IOD_EDEVICE. */
 int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *stream);
 
 /* Run n_iter further iterations of Algorithm 1 (n = s->iter + 1 ...): per
@@ -201,6 +249,10 @@ int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *s
  * (n, i, problem, 1), words 0 and 1), v <- omega v + eta1 r1 (p - x)
  * + eta2 r2 (g - x), x <- x + v with g the previous iteration's global best;
  * then the global best moves to the lowest personal best if strictly lower.
+ * The variants of iod_pso_params apply (p must match the one given to
+ * iod_swarm_init). With tol > 0 the swarm needs a history of at least
+ * s->iter + n_iter + 1 entries (Algorithm 2 reads it); once Algorithm 2 has
+ * ended the run, further iterations change nothing but the history (NaN).
  * Advances s->iter. n_iter = 0 is a no-op.
  * Errors: IOD_EINVAL, IOD_ESTATE, IOD_EDEVICE. */
 int iod_step(iod_handle *h, iod_swarm *s, const iod_pso_params *p, int64_t n_iter,
@@ -214,9 +266,10 @@ int iod_swarm_best(iod_handle *h, iod_swarm *s, double best_state[6], double *be
                    int64_t *best_index, void *stream);
 
 /* Whole solve: allocate an m-particle swarm, initialise, run n_iter
- * iterations, return the global best, free. history (host [n_iter + 1] or
- * NULL) receives the global-best cost after initialisation and after each
- * iteration. Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+ * iterations (fewer if Algorithm 2 ends the run), return the global best,
+ * free. history (host [n_iter + 1] or NULL) receives the global-best cost
+ * after initialisation and after each iteration (NaN after an Algorithm 2
+ * stop). Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
               double best_state[6], double *best_cost, double *history);
 
@@ -243,6 +296,17 @@ int iod_create_batch(int32_t n_problems, const double *mu, const double *chief_s
                      const double *obs_angles, const double *sigma, const iod_options *opt,
                      iod_batch **out);
 
+/* As iod_create_batch, with range measurements as in iod_create_ranged:
+ *   obs_ranges   host [obs_offsets[P]] observed ranges, or NULL (no ranges)
+ *   sigma_range  host [P]: > 0 for a problem with ranges, 0 for a problem
+ *                with angles only (its obs_ranges entries are ignored)
+ * sigma_range may be NULL only when obs_ranges is NULL. */
+int iod_create_batch_ranged(int32_t n_problems, const double *mu, const double *chief_states,
+                            const int64_t *obs_offsets, const double *obs_times,
+                            const double *obs_angles, const double *obs_ranges,
+                            const double *sigma, const double *sigma_range,
+                            const iod_options *opt, iod_batch **out);
+
 /* Release a batch (NULL is accepted). Synchronises the device. */
 int iod_batch_destroy(iod_batch *b);
 
@@ -263,6 +327,11 @@ int iod_batch_get_config(const iod_batch *b, iod_launch_config *cfg);
  *   angles  host [obs_offsets[P]][2], in the batch's observation layout
  * Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_batch_predict(iod_batch *b, const double *x, double *angles);
+
+/* Predicted ranges |rho| of one state per problem at that problem's
+ * observation times: ranges host [obs_offsets[P]]. Synchronous.
+ * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+int iod_batch_predict_ranges(iod_batch *b, const double *x, double *ranges);
 
 /* Column offsets of a batched swarm: problem p with m[p] >= 0 particles
  * owns columns off[p] .. off[p] + m[p] - 1 of a [6][ld] array, where
@@ -285,7 +354,9 @@ int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, 
  * streams), m host [P] >= 1 particles, n_iter iterations of Algorithm 1 for
  * all. Outputs (host): best_states [P][6], best_costs [P], and history
  * [P][n_iter + 1] or NULL. Problem p's results are bit-identical to
- * iod_solve on the same problem with params[p] and m[p]. Synchronous.
+ * iod_solve on the same problem with params[p] and m[p], the variants
+ * included; a problem that Algorithm 2 ends early stops taking device time
+ * (its workgroups exit at once) while the others go on. Synchronous.
  * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
                     double *best_states, double *best_costs, double *history);

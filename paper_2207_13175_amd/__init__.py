@@ -45,7 +45,13 @@ class iod_options(C.Structure):
 class iod_pso_params(C.Structure):
     _fields_ = [("omega", C.c_double), ("eta1", C.c_double), ("eta2", C.c_double),
                 ("seed", C.c_uint64), ("problem", C.c_uint64),
-                ("lo", C.c_double * 6), ("hi", C.c_double * 6)]
+                ("lo", C.c_double * 6), ("hi", C.c_double * 6),
+                ("flags", C.c_uint32), ("tol_lag", C.c_int32), ("tol", C.c_double)]
+
+
+IOD_PSO_CONSTRICTION = 1
+IOD_PSO_PER_DIM_R = 2
+IOD_PSO_GRID_INIT = 4
 
 
 class iod_swarm(C.Structure):
@@ -72,11 +78,15 @@ _SIGNATURES = {
     "iod_schedule": (C.c_int, [_D, C.c_int32, C.c_double, _I64, _D]),
     "iod_create": (C.c_int, [C.c_double, _D, _D, _D, C.c_int32, C.c_double,
                              C.POINTER(iod_options), C.POINTER(C.c_void_p)]),
+    "iod_create_ranged": (C.c_int, [C.c_double, _D, _D, _D, _D, C.c_int32, C.c_double, C.c_double,
+                                    C.POINTER(iod_options), C.POINTER(C.c_void_p)]),
     "iod_destroy": (C.c_int, [C.c_void_p]),
     "iod_num_obs": (C.c_int32, [C.c_void_p]),
     "iod_chief_positions": (C.c_int, [C.c_void_p, _D]),
     "iod_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "iod_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "iod_predict_ranges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                     C.c_void_p]),
     "iod_eval_swarm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "iod_swarm_work_len": (C.c_int64, [C.c_int64]),
     "iod_swarm_init": (C.c_int, [C.c_void_p, C.POINTER(iod_swarm), C.POINTER(iod_pso_params), C.c_void_p]),
@@ -87,6 +97,8 @@ _SIGNATURES = {
     "iod_get_config": (C.c_int, [C.c_void_p, C.POINTER(iod_launch_config)]),
     "iod_create_batch": (C.c_int, [C.c_int32, _D, _D, _I64, _D, _D, _D, C.POINTER(iod_options),
                                    C.POINTER(C.c_void_p)]),
+    "iod_create_batch_ranged": (C.c_int, [C.c_int32, _D, _D, _I64, _D, _D, _D, _D, _D,
+                                          C.POINTER(iod_options), C.POINTER(C.c_void_p)]),
     "iod_batch_destroy": (C.c_int, [C.c_void_p]),
     "iod_batch_size": (C.c_int32, [C.c_void_p]),
     "iod_batch_steps": (C.c_int64, [C.c_void_p, C.c_int32]),
@@ -106,6 +118,7 @@ _SIGNATURES = {
     "iod_batch_solve_mixed": (C.c_int, [C.c_void_p, C.POINTER(iod_pso_params), _I64, C.c_int64,
                                         C.c_int32, _D, _D, _D]),
     "iod_batch_predict": (C.c_int, [C.c_void_p, _D, _D]),
+    "iod_batch_predict_ranges": (C.c_int, [C.c_void_p, _D, _D]),
     "iod_grad_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
     "iod_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
@@ -212,6 +225,22 @@ def iod_create(mu, chief_state, obs_times, obs_angles, sigma, h=1e-3, cost_mode=
     return Handle(out, len(t))
 
 
+def iod_create_ranged(mu, chief_state, obs_times, obs_angles, obs_ranges, sigma, sigma_range,
+                      h=1e-3, cost_mode=IOD_COST_PAPER):
+    """As iod_create, with observed ranges [K] and their noise level."""
+    chief = np.ascontiguousarray(chief_state, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(obs_times, dtype=np.float64).ravel()
+    ang = np.ascontiguousarray(obs_angles, dtype=np.float64).reshape(-1)
+    rng = np.ascontiguousarray(obs_ranges, dtype=np.float64).ravel()
+    if chief.size != 6 or ang.size != 2 * t.size or rng.size != t.size:
+        raise ValueError("chief_state must have 6 values, obs_angles [K, 2], obs_ranges [K]")
+    opt = iod_options(float(h), int(cost_mode), 0)
+    out = C.c_void_p()
+    _check(lib().iod_create_ranged(float(mu), _dp(chief), _dp(t), _dp(ang), _dp(rng), len(t),
+                                   float(sigma), float(sigma_range), C.byref(opt), C.byref(out)))
+    return Handle(out, len(t))
+
+
 def iod_destroy(handle: Handle):
     if handle.ptr:
         rc = lib().iod_destroy(handle.ptr)
@@ -239,6 +268,13 @@ def iod_predict(handle: Handle, x, m, angles, stream=None):
                              _dev(angles, (handle.K, 2, ld)), _stream(stream)))
 
 
+def iod_predict_ranges(handle: Handle, x, m, ranges, stream=None):
+    """x: [6, ld] -> ranges: [K, ld]."""
+    ld = x.shape[1]
+    _check(lib().iod_predict_ranges(handle.ptr, _dev(x, (6, ld)), ld, int(m),
+                                    _dev(ranges, (handle.K, ld)), _stream(stream)))
+
+
 def iod_eval_swarm(handle: Handle, x, m, cost, stream=None):
     """x: [6, ld] -> cost: [ld] (first m written)."""
     ld = x.shape[1]
@@ -250,11 +286,15 @@ def iod_swarm_work_len(m) -> int:
     return _check(lib().iod_swarm_work_len(int(m)))
 
 
-def pso_params(omega, eta1, eta2, seed, lo, hi, problem=0) -> iod_pso_params:
+def pso_params(omega, eta1, eta2, seed, lo, hi, problem=0, flags=0, tol=0.0,
+               tol_lag=10) -> iod_pso_params:
+    """Algorithm 1 parameters; flags = IOD_PSO_* variants, tol > 0 turns on
+    Algorithm 2 with lag tol_lag."""
     lo = np.asarray(lo, dtype=np.float64).ravel()
     hi = np.asarray(hi, dtype=np.float64).ravel()
     return iod_pso_params(float(omega), float(eta1), float(eta2), int(seed), int(problem),
-                          (C.c_double * 6)(*lo), (C.c_double * 6)(*hi))
+                          (C.c_double * 6)(*lo), (C.c_double * 6)(*hi), int(flags),
+                          int(tol_lag), float(tol))
 
 
 class Swarm:
@@ -339,9 +379,12 @@ class Batch:
             self.ptr = None
 
 
-def iod_create_batch(mu, chief_states, obs_times, obs_angles, sigma, h=None, cost_mode=None):
+def iod_create_batch(mu, chief_states, obs_times, obs_angles, sigma, h=None, cost_mode=None,
+                     obs_ranges=None, sigma_range=None):
     """Lists per problem: mu [P], chief_states [P][6], obs_times [P][K_p],
-    obs_angles [P][K_p][2], sigma [P]; h and cost_mode scalars or per problem."""
+    obs_angles [P][K_p][2], sigma [P]; h and cost_mode scalars or per problem.
+    obs_ranges [P][K_p] (entries may be None) with sigma_range [P] (0 for a
+    problem without ranges) adds range measurements."""
     P = len(mu)
     K = np.array([len(t) for t in obs_times], dtype=np.int64)
     off = np.concatenate([[0], np.cumsum(K)]).astype(np.int64)
@@ -357,8 +400,17 @@ def iod_create_batch(mu, chief_states, obs_times, obs_angles, sigma, h=None, cos
         cm = np.broadcast_to(np.asarray(0 if cost_mode is None else cost_mode), (P,))
         opts = (iod_options * P)(*[iod_options(float(hh[p]), int(cm[p]), 0) for p in range(P)])
     out = C.c_void_p()
-    _check(lib().iod_create_batch(P, _dp(mu_a), _dp(ch), off.ctypes.data_as(_I64), _dp(t), _dp(ang),
-                                  _dp(sg), opts, C.byref(out)))
+    if obs_ranges is None:
+        _check(lib().iod_create_batch(P, _dp(mu_a), _dp(ch), off.ctypes.data_as(_I64), _dp(t),
+                                      _dp(ang), _dp(sg), opts, C.byref(out)))
+    else:
+        rg = np.ascontiguousarray(np.concatenate([
+            np.zeros(int(K[p])) if r is None else np.asarray(r, dtype=np.float64).ravel()
+            for p, r in enumerate(obs_ranges)]))
+        sr = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma_range, dtype=np.float64), (P,)))
+        _check(lib().iod_create_batch_ranged(P, _dp(mu_a), _dp(ch), off.ctypes.data_as(_I64),
+                                             _dp(t), _dp(ang), _dp(rg), _dp(sg), _dp(sr), opts,
+                                             C.byref(out)))
     return Batch(out, P, K)
 
 
@@ -389,6 +441,15 @@ def iod_batch_predict(batch: Batch, x):
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(batch.P, 6)
     out = np.empty((int(np.sum(batch.K)), 2))
     _check(lib().iod_batch_predict(batch.ptr, _dp(x), _dp(out)))
+    off = np.concatenate([[0], np.cumsum(batch.K)])
+    return [out[off[p]:off[p + 1]] for p in range(batch.P)]
+
+
+def iod_batch_predict_ranges(batch: Batch, x):
+    """Predicted ranges of one state per problem (x [P, 6]) -> list of [K_p]."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(batch.P, 6)
+    out = np.empty(int(np.sum(batch.K)))
+    _check(lib().iod_batch_predict_ranges(batch.ptr, _dp(x), _dp(out)))
     off = np.concatenate([[0], np.cumsum(batch.K)])
     return [out[off[p]:off[p + 1]] for p in range(batch.P)]
 

@@ -61,6 +61,7 @@ int64_t round64(int64_t a) { return ceil_div(a, 64) * 64; }
 // table rows (chief positions filled in on the device).
 struct HostProblem {
     double mu = 0, h = 0, sigma = 0;
+    double sigma_range = 0;     // > 0: range measurements in TAB_RANGE
     int32_t K = 0, mode = 0;
     double chief[6] = {0, 0, 0, 0, 0, 0};
     std::vector<double> tab;    // [K][TAB_W]
@@ -88,10 +89,18 @@ extern "C" int iod_schedule(const double *t, int32_t n_obs, double h, int64_t *n
 
 namespace {
 
-int make_problem(double mu, const double *chief, const double *t, const double *ang, int32_t K,
-                 double sigma, const iod_options *opt, HostProblem &P)
+int make_problem(double mu, const double *chief, const double *t, const double *ang,
+                 const double *ranges, int32_t K, double sigma, double sigma_range,
+                 const iod_options *opt, HostProblem &P)
 {
     if (!chief || !t || !ang) return fail(IOD_EINVAL, "null host pointer");
+    if (ranges) {
+        if (!(sigma_range > 0.0) || !std::isfinite(sigma_range))
+            return fail(IOD_EINVAL, "sigma_range must be positive and finite");
+        for (int32_t k = 0; k < K; ++k)
+            if (!std::isfinite(ranges[k]) || ranges[k] < 0.0)
+                return fail(IOD_EINVAL, "obs_ranges[%d] invalid", k);
+    }
     if (!std::isfinite(mu) || mu < 0.0 || mu > 0.5) return fail(IOD_EINVAL, "mu must lie in [0, 0.5]");
     if (!finite6(chief)) return fail(IOD_EINVAL, "non-finite chief state");
     if (!(sigma > 0.0) || !std::isfinite(sigma))
@@ -111,6 +120,7 @@ int make_problem(double mu, const double *chief, const double *t, const double *
     P.mu = mu;
     P.h = o.h;
     P.sigma = sigma;
+    P.sigma_range = ranges ? sigma_range : 0.0;
     P.K = K;
     P.mode = o.cost_mode;
     std::memcpy(P.chief, chief, sizeof P.chief);
@@ -125,6 +135,7 @@ int make_problem(double mu, const double *chief, const double *t, const double *
         row[TAB_CA] = std::cos(ang[2 * k]);
         row[TAB_SB] = std::sin(ang[2 * k + 1]);
         row[TAB_CB] = std::cos(ang[2 * k + 1]);
+        row[TAB_RANGE] = ranges ? ranges[k] : 0.0;
     }
     P.steps = ns[K - 1] + (tau[K - 1] != 0.0 ? 1 : 0);
     return IOD_OK;
@@ -144,7 +155,40 @@ KArgs kargs_of(const HostProblem &P, const double *d_tab, const int32_t *d_ns)
     A.h2 = 0.5 * P.h;
     A.h6 = P.h / 6.0;
     A.w = 1.0 / (P.sigma * P.sigma);
+    A.wr = P.sigma_range > 0.0 ? 1.0 / (P.sigma_range * P.sigma_range) : 0.0;
     return A;
+}
+
+// Levels per dimension of the grid initialisation for m particles: b levels
+// everywhere with b^6 <= m < (b+1)^6, then dimensions 0, 1, ... raised to
+// b + 1 while the product stays <= m. Returns the product.
+int64_t grid_levels(int64_t m, int64_t n[6])
+{
+    int64_t b = 1;
+    while (true) {
+        const int64_t c = b + 1;
+        int64_t pw = 1;
+        for (int d = 0; d < 6; ++d) pw *= c;
+        if (pw > m) break;
+        b = c;
+    }
+    int64_t g = 1;
+    for (int d = 0; d < 6; ++d) {
+        n[d] = b;
+        g *= b;
+    }
+    for (int d = 0; d < 6 && g / b * (b + 1) <= m; ++d) {
+        g = g / b * (b + 1);
+        n[d] = b + 1;
+    }
+    return g;
+}
+
+// Constriction factor for phi = eta1 + eta2 > 4 (eq. constriction:factor).
+double constriction(double eta1, double eta2)
+{
+    const double phi = eta1 + eta2;
+    return 2.0 / std::fabs(2.0 - phi - std::sqrt(phi * phi - 4.0 * phi));
 }
 
 ProbDesc desc_of(const KArgs &A, const double chief[6], const iod_pso_params *p)
@@ -153,6 +197,7 @@ ProbDesc desc_of(const KArgs &A, const double chief[6], const iod_pso_params *p)
     std::memset(&D, 0, sizeof D);
     D.k = A;
     std::memcpy(D.chief, chief, sizeof D.chief);
+    D.kappa = 1.0;
     if (p) {
         D.omega = p->omega;
         D.eta1 = p->eta1;
@@ -161,8 +206,19 @@ ProbDesc desc_of(const KArgs &A, const double chief[6], const iod_pso_params *p)
         std::memcpy(D.hi, p->hi, sizeof D.hi);
         D.seed = p->seed;
         D.problem = p->problem;
+        D.flags = p->flags & PSO_PER_DIM_R;
+        if (p->flags & IOD_PSO_CONSTRICTION) D.kappa = constriction(p->eta1, p->eta2);
+        D.tol = p->tol;
+        D.tol_lag = p->tol > 0.0 ? p->tol_lag : 0;
     }
     return D;
+}
+
+// Grid levels of a swarm of m particles, when the initialisation asks for it.
+void set_grid(ProbDesc &D, const iod_pso_params *p, int64_t m)
+{
+    D.grid_g = 0;
+    if (p && (p->flags & IOD_PSO_GRID_INIT) && m >= 1) D.grid_g = grid_levels(m, D.grid_n);
 }
 
 int check_pso(const iod_pso_params *p)
@@ -173,6 +229,12 @@ int check_pso(const iod_pso_params *p)
     if (!finite6(p->lo) || !finite6(p->hi)) return fail(IOD_EINVAL, "non-finite box");
     for (int d = 0; d < 6; ++d)
         if (p->lo[d] > p->hi[d]) return fail(IOD_EINVAL, "lo[%d] > hi[%d]", d, d);
+    const uint32_t known = IOD_PSO_CONSTRICTION | IOD_PSO_PER_DIM_R | IOD_PSO_GRID_INIT;
+    if (p->flags & ~known) return fail(IOD_EINVAL, "unknown flags 0x%x", p->flags & ~known);
+    if ((p->flags & IOD_PSO_CONSTRICTION) && !(p->eta1 + p->eta2 > 4.0))
+        return fail(IOD_EINVAL, "constriction factor needs eta1 + eta2 > 4");
+    if (!std::isfinite(p->tol) || p->tol < 0.0) return fail(IOD_EINVAL, "tol must be finite and >= 0");
+    if (p->tol > 0.0 && p->tol_lag < 1) return fail(IOD_EINVAL, "tol_lag must be >= 1");
     return IOD_OK;
 }
 
@@ -319,6 +381,8 @@ void single_view(const iod_handle *h, const iod_swarm *s, const iod_pso_params *
     B.cost = s->cost;
     B.slots = s->work;
     B.recs = s->work + 2 * nslots * REC;
+    B.stop = B.recs + 2 * REC;
+    set_grid(D, p, s->m);
     B.ld = s->ld;
     B.total_slots = nslots;
     B.nprob = 1;
@@ -328,7 +392,7 @@ void single_view(const iod_handle *h, const iod_swarm *s, const iod_pso_params *
 
 extern "C" {
 
-int iod_version(void) { return 10100; }
+int iod_version(void) { return 10200; }
 
 const char *iod_last_error(void) { return g_err; }
 
@@ -363,10 +427,20 @@ int iod_create(double mu, const double chief_state[6], const double *obs_times,
                const double *obs_angles, int32_t n_obs, double sigma, const iod_options *opt,
                iod_handle **out)
 {
+    return iod_create_ranged(mu, chief_state, obs_times, obs_angles, nullptr, n_obs, sigma, 0.0,
+                             opt, out);
+}
+
+int iod_create_ranged(double mu, const double chief_state[6], const double *obs_times,
+                      const double *obs_angles, const double *obs_ranges, int32_t n_obs,
+                      double sigma, double sigma_range, const iod_options *opt,
+                      iod_handle **out)
+{
     if (!out) return fail(IOD_EINVAL, "null out");
     *out = nullptr;
     HostProblem P;
-    int rc = make_problem(mu, chief_state, obs_times, obs_angles, n_obs, sigma, opt, P);
+    int rc = make_problem(mu, chief_state, obs_times, obs_angles, obs_ranges, n_obs, sigma,
+                          sigma_range, opt, P);
     if (rc != IOD_OK) return rc;
     iod_handle *h = new (std::nothrow) iod_handle;
     if (!h) return fail(IOD_ENOMEM, "host allocation");
@@ -461,6 +535,16 @@ int iod_predict(iod_handle *h, const double *x, int64_t ld, int64_t m, double *a
     return IOD_OK;
 }
 
+int iod_predict_ranges(iod_handle *h, const double *x, int64_t ld, int64_t m, double *ranges,
+                       void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, ranges);
+    if (rc != IOD_OK || m == 0) return rc;
+    HIP_TRY(launch_predict_ranges(h->kargs(), x, ld, m, ranges, (hipStream_t)stream));
+    return IOD_OK;
+}
+
 int iod_eval_swarm(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost,
                    void *stream)
 {
@@ -485,7 +569,7 @@ int iod_eval_swarm(iod_handle *h, const double *x, int64_t ld, int64_t m, double
 int64_t iod_swarm_work_len(int64_t m)
 {
     if (m < 1 || m > MAX_M) return fail(IOD_EINVAL, "m = %lld out of range", (long long)m);
-    return 2 * ceil_div(m, 64) * REC + 2 * REC;
+    return 2 * ceil_div(m, 64) * REC + 3 * REC;
 }
 
 int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *stream)
@@ -511,6 +595,9 @@ int iod_step(iod_handle *h, iod_swarm *s, const iod_pso_params *p, int64_t n_ite
     if (rc == IOD_OK) rc = check_pso(p);
     if (rc != IOD_OK) return rc;
     if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    if (p->tol > 0.0 && (!s->hist || s->hist_len < s->iter + n_iter + 1))
+        return fail(IOD_EINVAL, "Algorithm 2 (tol > 0) needs a history of >= %lld entries",
+                    (long long)(s->iter + n_iter + 1));
     ProbDesc D;
     SwarmArrays B;
     single_view(h, s, p, D, B);
@@ -598,11 +685,22 @@ int iod_create_batch(int32_t n_problems, const double *mu, const double *chief_s
                      const double *obs_angles, const double *sigma, const iod_options *opt,
                      iod_batch **out)
 {
+    return iod_create_batch_ranged(n_problems, mu, chief_states, obs_offsets, obs_times,
+                                   obs_angles, nullptr, sigma, nullptr, opt, out);
+}
+
+int iod_create_batch_ranged(int32_t n_problems, const double *mu, const double *chief_states,
+                            const int64_t *obs_offsets, const double *obs_times,
+                            const double *obs_angles, const double *obs_ranges,
+                            const double *sigma, const double *sigma_range,
+                            const iod_options *opt, iod_batch **out)
+{
     if (!out) return fail(IOD_EINVAL, "null out");
     *out = nullptr;
     if (n_problems < 1) return fail(IOD_EINVAL, "n_problems = %d < 1", n_problems);
     if (!mu || !chief_states || !obs_offsets || !obs_times || !obs_angles || !sigma)
         return fail(IOD_EINVAL, "null host pointer");
+    if (obs_ranges && !sigma_range) return fail(IOD_EINVAL, "obs_ranges given without sigma_range");
     if (obs_offsets[0] != 0) return fail(IOD_EINVAL, "obs_offsets[0] must be 0");
     iod_batch *b = new (std::nothrow) iod_batch;
     if (!b) return fail(IOD_ENOMEM, "host allocation");
@@ -618,9 +716,11 @@ int iod_create_batch(int32_t n_problems, const double *mu, const double *chief_s
         const int64_t K = obs_offsets[p + 1] - obs_offsets[p];
         if (K < 1 || K > IOD_MAX_OBS)
             return bail(fail(IOD_EINVAL, "problem %d: %lld observations", p, (long long)K));
+        const bool ranged = obs_ranges && sigma_range[p] != 0.0;
         int rc = make_problem(mu[p], chief_states + 6 * (size_t)p, obs_times + obs_offsets[p],
-                              obs_angles + 2 * obs_offsets[p], (int32_t)K, sigma[p],
-                              opt ? opt + p : nullptr, b->probs[p]);
+                              obs_angles + 2 * obs_offsets[p],
+                              ranged ? obs_ranges + obs_offsets[p] : nullptr, (int32_t)K, sigma[p],
+                              ranged ? sigma_range[p] : 0.0, opt ? opt + p : nullptr, b->probs[p]);
         if (rc != IOD_OK) {
             char msg[512];
             std::snprintf(msg, sizeof msg, "%s", g_err);
@@ -738,6 +838,7 @@ int batch_layout(const iod_batch *b, const iod_pso_params *params, const int64_t
     for (int32_t p = 0; p < b->P; ++p) {
         ProbDesc &D = L.descs[p];
         D = desc_of(b->kargs(p), b->probs[p].chief, params ? params + p : nullptr);
+        set_grid(D, params ? params + p : nullptr, m[p]);
         D.m = m[p];
         D.off = off[p];
         D.slot_off = slots;
@@ -785,7 +886,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     int rc = batch_layout(b, params, m, bs, cfg.order, L);
     if (rc != IOD_OK) return rc;
     const int64_t P = b->P, ld = L.ld;
-    const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1));
+    const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1) + P);
     Stream st;
     DevBuf dbuf, ddesc, dwork, dcand;
     HIP_TRY(hipStreamCreate(&st.s));
@@ -794,6 +895,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     int32_t *cand = (int32_t *)dcand.p;
     double *base = (double *)dbuf.p;
     double *hist = base + 20 * ld + 2 * L.total_slots * REC + 2 * P * REC;
+    double *stop = hist + P * (n_iter + 1);
     for (int64_t p = 0; p < P; ++p) {
         L.descs[p].hist = hist + p * (n_iter + 1);
         L.descs[p].hist_len = n_iter + 1;
@@ -812,6 +914,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     B.cost = base + 19 * ld;
     B.slots = base + 20 * ld;
     B.recs = B.slots + 2 * L.total_slots * REC;
+    B.stop = stop;
     B.ld = ld;
     B.total_slots = L.total_slots;
     B.nprob = P;
@@ -1204,33 +1307,48 @@ void single_cols(const iod_handle *h, const double *x, int64_t ld, int64_t m, in
     B.nprob = 1;
 }
 
-}  // namespace
-
-extern "C" {
-
-int iod_batch_predict(iod_batch *b, const double *x, double *angles)
+int batch_predict_impl(iod_batch *b, const double *x, double *out, bool ranges)
 {
     int rc = check_batch(b);
     if (rc != IOD_OK) return rc;
-    if (!x || !angles) return fail(IOD_EINVAL, "null host pointer");
+    if (!x || !out) return fail(IOD_EINVAL, "null host pointer");
     const int64_t P = b->P;
     for (int64_t p = 0; p < P; ++p)
         if (!finite6(x + 6 * p)) return fail(IOD_EINVAL, "problem %lld: non-finite state", (long long)p);
     const int64_t rows = b->tab_off[P - 1] + b->probs[P - 1].K;
+    const int64_t per_row = ranges ? 1 : 2;
     std::vector<ProbDesc> descs(P);
     for (int64_t p = 0; p < P; ++p) descs[p] = desc_of(b->kargs((int32_t)p), b->probs[p].chief, nullptr);
     DevBuf dd, dx, doff, dout;
     HIP_TRY(hipMalloc(&dd.p, P * sizeof(ProbDesc)));
     HIP_TRY(hipMalloc(&dx.p, 6 * P * sizeof(double)));
     HIP_TRY(hipMalloc(&doff.p, P * sizeof(int64_t)));
-    HIP_TRY(hipMalloc(&dout.p, 2 * rows * sizeof(double)));
+    HIP_TRY(hipMalloc(&dout.p, per_row * rows * sizeof(double)));
     HIP_TRY(hipMemcpy(dd.p, descs.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dx.p, x, 6 * P * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(doff.p, b->tab_off.data(), P * sizeof(int64_t), hipMemcpyHostToDevice));
-    HIP_TRY(launch_predict_batch((const ProbDesc *)dd.p, P, (const double *)dx.p,
-                                 (const int64_t *)doff.p, (double *)dout.p, nullptr));
-    HIP_TRY(hipMemcpy(angles, dout.p, 2 * rows * sizeof(double), hipMemcpyDeviceToHost));
+    if (ranges)
+        HIP_TRY(launch_predict_ranges_batch((const ProbDesc *)dd.p, P, (const double *)dx.p,
+                                            (const int64_t *)doff.p, (double *)dout.p, nullptr));
+    else
+        HIP_TRY(launch_predict_batch((const ProbDesc *)dd.p, P, (const double *)dx.p,
+                                     (const int64_t *)doff.p, (double *)dout.p, nullptr));
+    HIP_TRY(hipMemcpy(out, dout.p, per_row * rows * sizeof(double), hipMemcpyDeviceToHost));
     return IOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iod_batch_predict(iod_batch *b, const double *x, double *angles)
+{
+    return batch_predict_impl(b, x, angles, false);
+}
+
+int iod_batch_predict_ranges(iod_batch *b, const double *x, double *ranges)
+{
+    return batch_predict_impl(b, x, ranges, true);
 }
 
 int64_t iod_grad_work_len(const iod_handle *h, int64_t ld)

@@ -12,9 +12,10 @@ namespace iodk {
 //   [1] partial step tau (0 when the observation is on the grid)
 //   [2..4] chief position at the observation time
 //   [5..8] sin(az_obs), cos(az_obs), sin(el_obs), cos(el_obs)
-//   [9] padding
+//   [9] observed range (0 when the problem has angles only)
 constexpr int TAB_W = 10;
 constexpr int TAB_NS = 0, TAB_TAU = 1, TAB_RC = 2, TAB_SA = 5, TAB_CA = 6, TAB_SB = 7, TAB_CB = 8;
+constexpr int TAB_RANGE = 9;
 
 // Rows staged in LDS at a time by every workgroup.
 constexpr int OBS_CHUNK = 64;
@@ -32,12 +33,22 @@ struct KArgs {
     double mu, mu1;     // mu and 1 - mu
     double h, h2, h6;   // h, h/2, h/6
     double w;           // 1 / sigma^2
+    double wr;          // 1 / sigma_range^2, 0 = angles only
 };
+
+// Swarm variants (bits of ProbDesc::flags; the values of iod.h's IOD_PSO_*).
+constexpr uint32_t PSO_PER_DIM_R = 2u;
 
 // One problem of a swarm launch (a single problem or one member of a batch).
 struct ProbDesc {
     KArgs k;
     double omega, eta1, eta2;   // Algorithm 1 weights
+    double kappa;               // constriction factor (1 when off)
+    double tol;                 // Algorithm 2 tolerance, 0 = off
+    int32_t tol_lag;            // Algorithm 2 lag
+    uint32_t flags;             // PSO_PER_DIM_R
+    int64_t grid_n[6];          // grid initialisation levels per dimension
+    int64_t grid_g;             // grid points (particles below it sit on the grid), 0 = off
     double lo[6], hi[6];        // initialisation box
     double chief[6];            // chief state at t = 0
     uint64_t seed, problem;     // Philox key word 0, counter word 2
@@ -58,6 +69,7 @@ struct SwarmArrays {
     double *x, *v, *p, *jp, *cost;  // [6][ld] / [ld] structure of arrays
     double *slots;              // [2][total_slots][REC]
     double *recs;               // [2][nprob][REC]
+    double *stop;               // [nprob] Algorithm 2: -1 running, else the last iteration run
     int64_t ld, total_slots, nprob;
 };
 
@@ -69,6 +81,11 @@ hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m
 // (row_off [nprob] first row of each problem).
 hipError_t launch_predict_batch(const ProbDesc *descs, int64_t nprob, const double *xs,
                                 const int64_t *row_off, double *out, hipStream_t st);
+// Ranges |rho| instead of angles: out [K][ld] (single), [rows] (batch).
+hipError_t launch_predict_ranges(const KArgs &A, const double *x, int64_t ld, int64_t m,
+                                 double *ranges, hipStream_t st);
+hipError_t launch_predict_ranges_batch(const ProbDesc *descs, int64_t nprob, const double *xs,
+                                       const int64_t *row_off, double *out, hipStream_t st);
 // descs == null: the single problem d0.
 hipError_t launch_chief(const ProbDesc &d0, const ProbDesc *descs, int64_t nprob, hipStream_t st);
 // bs in {64, 128, 256}; grid = workgroups (nslots for a single problem).

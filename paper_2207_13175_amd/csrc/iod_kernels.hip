@@ -213,6 +213,7 @@ __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, i
 struct CostAcc {
     double J, w;
     int32_t mode;
+    double wr;   // range weight, 0 = angles only
     __device__ __forceinline__ void operator()(const double *row, const double S[6])
     {
         const double rx = S[0] - row[TAB_RC + 0];
@@ -235,6 +236,11 @@ struct CostAcc {
             const double da = atan2(na, nd);
             const double db = atan2(fma(sb, rxy, -(cb * rz)), fma(cb, rxy, sb * rz));
             e = w * fma(da, da, db * db);
+            if (wr != 0.0) {
+                // range residual: observed minus |rho|
+                const double dr = row[TAB_RANGE] - sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+                e = fma(wr * dr, dr, e);
+            }
         }
         J = (mode == 1) ? J + e : fma(e, e, J);
     }
@@ -246,7 +252,7 @@ __device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], 
     double X[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = x0[d];
-    CostAcc acc{0.0, A.w, A.mode};
+    CostAcc acc{0.0, A.w, A.mode, A.wr};
     walk(A, X, lds, lds_ns, acc);
     return acc.J;
 }
@@ -277,6 +283,89 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 }
 
 __device__ __forceinline__ double u01(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+
+// ---------------------------------------------------------------------------
+// Particle swarm building blocks (Algorithm 1 and its variants).
+// ---------------------------------------------------------------------------
+
+// Initial position of particle j (its velocity is zero). With the grid
+// initialisation, particles j < grid_g sit on the cell centres of a
+// Cartesian grid over the box: j's mixed-radix digits (dimension 0 fastest)
+// give u_d = (2 j_d + 1) / (2 n_d). Otherwise u is uniform, words 0-5 of
+// Philox counters (0, j, problem, 0) and (1, j, problem, 0).
+__device__ __forceinline__ void init_state(const ProbDesc &D, int64_t j, double X[6])
+{
+    double u[6];
+    if (j < D.grid_g) {
+        int64_t q = j;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int64_t nd = D.grid_n[d];
+            const int64_t jd = q % nd;
+            q /= nd;
+            u[d] = (double)(2 * jd + 1) / (double)(2 * nd);
+        }
+    } else {
+        uint64_t w[8] = {0, (uint64_t)j, D.problem, 0, 1, (uint64_t)j, D.problem, 0};
+        philox4x64_10(w, D.seed, 0);
+        philox4x64_10(w + 4, D.seed, 0);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) u[d] = u01(w[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = D.lo[d] + (D.hi[d] - D.lo[d]) * u[d];
+}
+
+// Velocity and position update of particle j at iteration n towards its
+// personal best Pb and the global best g:
+//   v <- kappa (omega v + eta1 r1 (Pb - x) + eta2 r2 (g - x)),  x <- x + v,
+// with kappa = 1 unless the constriction factor is on. r1, r2: words 0 and 1
+// of Philox counter (n, j, problem, 1); per dimension, words 2d and 2d + 1
+// of counters (n, j, problem, 2), (.., 3), (.., 4).
+__device__ __forceinline__ void pso_update(const ProbDesc &D, int64_t n, int64_t j, double X[6],
+                                           double V[6], const double Pb[6], const double g[6])
+{
+    double a1[6], a2[6];
+    if (D.flags & PSO_PER_DIM_R) {
+        uint64_t w[12];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            w[4 * b + 0] = (uint64_t)n;
+            w[4 * b + 1] = (uint64_t)j;
+            w[4 * b + 2] = D.problem;
+            w[4 * b + 3] = 2 + (uint64_t)b;
+            philox4x64_10(w + 4 * b, D.seed, 0);
+        }
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            a1[d] = D.eta1 * u01(w[2 * d]);
+            a2[d] = D.eta2 * u01(w[2 * d + 1]);
+        }
+    } else {
+        uint64_t c[4] = {(uint64_t)n, (uint64_t)j, D.problem, 1};
+        philox4x64_10(c, D.seed, 0);
+        const double s1 = D.eta1 * u01(c[0]), s2 = D.eta2 * u01(c[1]);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            a1[d] = s1;
+            a2[d] = s2;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const double vn = D.kappa * (D.omega * V[d] + a1[d] * (Pb[d] - X[d]) + a2[d] * (g[d] - X[d]));
+        V[d] = vn;
+        X[d] = X[d] + vn;
+    }
+}
+
+// Algorithm 2's test on the global-best costs of iterations n and n - L:
+// K = |(jn - jl) / jn| < tau, with equal costs counted as K = 0.
+__device__ __forceinline__ bool tolerance_met(double jn, double jl, double tau)
+{
+    const double K = (jn == jl) ? 0.0 : fabs((jn - jl) / jn);
+    return K < tau;
+}
 
 // ---------------------------------------------------------------------------
 // Argmin reductions: lexicographic (key, index), NaN ranked as +inf.
@@ -532,6 +621,77 @@ hipError_t launch_predict_batch(const ProbDesc *descs, int64_t nprob, const doub
     return hipGetLastError();
 }
 
+// Predicted ranges |rho| (the range entry of the measurement function):
+// out[k * ld + i] for a swarm, out[row] for one state per problem.
+__device__ __forceinline__ double range_literal(const double *row, const double S[6])
+{
+    const double rx = S[0] - row[TAB_RC + 0];
+    const double ry = S[1] - row[TAB_RC + 1];
+    const double rz = S[2] - row[TAB_RC + 2];
+    return sqrt(rx * rx + ry * ry + rz * rz);
+}
+
+struct StoreRanges {
+    double *out;
+    int64_t ld, i;
+    int32_t k;
+    bool valid;
+    __device__ __forceinline__ void operator()(const double *row, const double S[6])
+    {
+        const double r = range_literal(row, S);
+        if (valid) out[(int64_t)k * ld + i] = r;
+        ++k;
+    }
+};
+
+struct StoreRangesRow {
+    double *out;
+    int32_t k;
+    __device__ __forceinline__ void operator()(const double *row, const double S[6])
+    {
+        const double r = range_literal(row, S);
+        if (threadIdx.x == 0) out[k] = r;
+        ++k;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_predict_ranges(KArgs A, const double *__restrict__ x,
+                                                        int64_t ld, int64_t m,
+                                                        double *__restrict__ out)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < m;
+    double X[6];
+    load_state(x, ld, valid ? i : m - 1, X);
+    StoreRanges obs{out, ld, i, 0, valid};
+    walk(A, X, lds, lds_ns, obs);
+}
+
+__global__ __launch_bounds__(64) void k_predict_ranges_batch(const ProbDesc *__restrict__ descs,
+                                                             const double *__restrict__ xs,
+                                                             const int64_t *__restrict__ row_off,
+                                                             double *__restrict__ out)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    const int64_t p = blockIdx.x;
+    double X[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = xs[6 * p + d];
+    StoreRangesRow obs{out + row_off[p], 0};
+    walk(descs[p].k, X, lds, lds_ns, obs);
+}
+
+hipError_t launch_predict_ranges_batch(const ProbDesc *descs, int64_t nprob, const double *xs,
+                                       const int64_t *row_off, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_predict_ranges_batch, dim3((unsigned)nprob), dim3(64), 0, st, descs, xs,
+                       row_off, out);
+    return hipGetLastError();
+}
+
 // One workgroup per problem; the chief is propagated with the particle
 // integrator and schedule (its positions do not enter the propagation).
 template <bool SINGLE>
@@ -575,12 +735,8 @@ __global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
     const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     const int64_t j = valid ? i : D.m - 1;
-    uint64_t u[8] = {0, (uint64_t)j, D.problem, 0, 1, (uint64_t)j, D.problem, 0};
-    philox4x64_10(u, D.seed, 0);
-    philox4x64_10(u + 4, D.seed, 0);
     double X[6];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) X[d] = D.lo[d] + (D.hi[d] - D.lo[d]) * u01(u[d]);
+    init_state(D, j, X);
     const double J = eval_cost(D.k, X, lds, lds_ns);
     const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
@@ -597,6 +753,7 @@ __global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
     write_slot(J, i, valid, X, B.slots + (D.slot_off + tile) * REC, red, wst);
     if (tile == 0 && threadIdx.x < REC)
         B.recs[(B.nprob + p) * REC + threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
+    if (tile == 0 && threadIdx.x == 0) B.stop[p] = -1.0;
 }
 
 // Algorithm 1, iteration n >= 1.
@@ -611,14 +768,31 @@ __global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, i
     const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
     const double *slots_prev = B.slots + (((n - 1) & 1) * B.total_slots + D.slot_off) * REC;
     double *slot_cur = B.slots + ((n & 1) * B.total_slots + D.slot_off + tile) * REC;
+    double *rec_prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;   // record n - 1
+    const double *rec_old = B.recs + ((n & 1) * B.nprob + p) * REC;    // record n - 2
+
+    // Algorithm 2 ended this problem in an earlier launch: carry its final
+    // record forward; the swarm stays as it was.
+    if (B.stop[p] >= 0.0) {
+        if (tile == 0) {
+            if (threadIdx.x < REC) rec_prev[threadIdx.x] = rec_old[threadIdx.x];
+            if (threadIdx.x == 0 && D.hist && n - 1 < D.hist_len) D.hist[n - 1] = NAN;
+        }
+        return;
+    }
 
     // (a) global best of the previous iteration
     double g[6], gkey, gidx;
-    reduce_global(slots_prev, D.nslots, B.recs + ((n & 1) * B.nprob + p) * REC, g, gkey, gidx,
-                  red);
+    reduce_global(slots_prev, D.nslots, rec_old, g, gkey, gidx, red);
     if (tile == 0) {
-        write_record(B.recs + (((n - 1) & 1) * B.nprob + p) * REC, g, gkey, gidx);
+        write_record(rec_prev, g, gkey, gidx);
         if (threadIdx.x == 0 && D.hist && n - 1 < D.hist_len) D.hist[n - 1] = gkey;
+    }
+    // Algorithm 2 after iteration n - 1 (every workgroup takes the same
+    // decision from the same record and history)
+    if (D.tol > 0.0 && n - 1 > D.tol_lag && tolerance_met(gkey, D.hist[n - 1 - D.tol_lag], D.tol)) {
+        if (tile == 0 && threadIdx.x == 0) B.stop[p] = (double)(n - 1);
+        return;
     }
 
     // (b) evaluate, personal best, velocity and position
@@ -642,16 +816,7 @@ __global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, i
 #pragma unroll
         for (int d = 0; d < 6; ++d) Pb[d] = X[d];
     }
-    uint64_t c[4] = {(uint64_t)n, (uint64_t)j, D.problem, 1};
-    philox4x64_10(c, D.seed, 0);
-    const double a1 = D.eta1 * u01(c[0]);
-    const double a2 = D.eta2 * u01(c[1]);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        const double vn = D.omega * V[d] + a1 * (Pb[d] - X[d]) + a2 * (g[d] - X[d]);
-        V[d] = vn;
-        X[d] = X[d] + vn;
-    }
+    pso_update(D, n, j, X, V, Pb, g);
     if (valid) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
@@ -678,6 +843,14 @@ __global__ __launch_bounds__(256) void k_swarm_final(ProbDesc d0, SwarmArrays B,
     __shared__ double red[2 * (256 / 64)];
     const int64_t p = SINGLE ? 0 : blockIdx.x;
     const ProbDesc &D = SINGLE ? d0 : B.desc[p];
+    if (B.stop[p] >= 0.0) {
+        // ended by Algorithm 2: the final record is record n - 1
+        const double *src = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
+        double *dst = B.recs + ((n & 1) * B.nprob + p) * REC;
+        if (threadIdx.x < REC) dst[threadIdx.x] = src[threadIdx.x];
+        if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = NAN;
+        return;
+    }
     double g[6], gkey, gidx;
     // slot geometry is that of the swarm kernels (D.block threads per slot)
     double key = INFINITY, idx = INFINITY;
@@ -809,6 +982,7 @@ struct CostAcc32 {
     double J;
     float w;
     int32_t mode;
+    float wr;   // range weight, 0 = angles only
     __device__ __forceinline__ void operator()(const double *row, const float S[6], const float C[6])
     {
         float r[3];
@@ -837,6 +1011,10 @@ struct CostAcc32 {
             const float da = atan2f(na, nd);
             const float db = atan2f(fmaf(sb, rxy, -(cb * r[2])), fmaf(cb, rxy, sb * r[2]));
             e = w * fmaf(da, da, db * db);
+            if (wr != 0.0f) {
+                const float dr = (float)row[TAB_RANGE] - sqrtf(fmaf(r[0], r[0], fmaf(r[1], r[1], r[2] * r[2])));
+                e = fmaf(wr * dr, dr, e);
+            }
         }
         const double ed = e;
         J = (mode == 1) ? J + ed : fma(ed, ed, J);
@@ -852,7 +1030,7 @@ __device__ __forceinline__ double eval_cost32(const KArgs &A, const double x0[6]
         X[d] = (float)x0[d];
         C[d] = -(float)(x0[d] - (double)X[d]);   // X - C carries x0 to ~2^-48
     }
-    CostAcc32 acc{0.0, (float)A.w, A.mode};
+    CostAcc32 acc{0.0, (float)A.w, A.mode, (float)A.wr};
     walk32(A, X, C, lds, lds_ns, acc);
     return acc.J;
 }
@@ -920,12 +1098,8 @@ __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
     const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     const int64_t j = valid ? i : D.m - 1;
-    uint64_t u[8] = {0, (uint64_t)j, D.problem, 0, 1, (uint64_t)j, D.problem, 0};
-    philox4x64_10(u, D.seed, 0);
-    philox4x64_10(u + 4, D.seed, 0);
     double X[6];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) X[d] = D.lo[d] + (D.hi[d] - D.lo[d]) * u01(u[d]);
+    init_state(D, j, X);
     const double J = eval_cost32(D.k, X, lds, lds_ns);
     const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
@@ -940,6 +1114,7 @@ __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
     }
     if (tile == 0 && threadIdx.x < REC)
         B.recs[(B.nprob + p) * REC + threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
+    if (tile == 0 && threadIdx.x == 0) B.stop[p] = -1.0;
 }
 
 // Mixed-precision iteration n >= 1: FP32 evaluation and personal best, then
@@ -951,6 +1126,7 @@ __global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, i
     __shared__ int32_t lds_ns[OBS_CHUNK];
     int64_t p, tile;
     const ProbDesc &D = locate<false>(d0, B, p, tile);
+    if (B.stop[p] >= 0.0) return;   // ended by Algorithm 2
     const double *rec = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
     double g[6];
 #pragma unroll
@@ -971,16 +1147,7 @@ __global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, i
 #pragma unroll
         for (int d = 0; d < 6; ++d) Pb[d] = X[d];
     }
-    uint64_t c[4] = {(uint64_t)n, (uint64_t)j, D.problem, 1};
-    philox4x64_10(c, D.seed, 0);
-    const double a1 = D.eta1 * u01(c[0]);
-    const double a2 = D.eta2 * u01(c[1]);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        const double vn = D.omega * V[d] + a1 * (Pb[d] - X[d]) + a2 * (g[d] - X[d]);
-        V[d] = vn;
-        X[d] = X[d] + vn;
-    }
+    pso_update(D, n, j, X, V, Pb, g);
     if (valid) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) {
@@ -1058,6 +1225,14 @@ __global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *_
     __shared__ double wst[6];
     const int64_t p = blockIdx.x;
     const ProbDesc &D = B.desc[p];
+    const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
+    double *cur = B.recs + ((n & 1) * B.nprob + p) * REC;
+    if (B.stop[p] >= 0.0) {
+        // ended by Algorithm 2: carry the final record forward
+        if (threadIdx.x < REC) cur[threadIdx.x] = prev[threadIdx.x];
+        if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = NAN;
+        return;
+    }
     double bkey = INFINITY, bidx = INFINITY, bst[6] = {0, 0, 0, 0, 0, 0};
     for (int c0 = 0; c0 < top_k; c0 += 64) {
         const int c = c0 + (int)threadIdx.x;
@@ -1081,7 +1256,6 @@ __global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *_
         for (int d = 0; d < 6; ++d) wst[d] = bst[d];
     }
     __syncthreads();
-    const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
     double g[6], gkey, gidx;
     if (idx < INFINITY && (prev[1] < 0.0 || key < prev[0])) {
         gkey = key;
@@ -1094,8 +1268,12 @@ __global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *_
 #pragma unroll
         for (int d = 0; d < 6; ++d) g[d] = prev[2 + d];
     }
-    write_record(B.recs + ((n & 1) * B.nprob + p) * REC, g, gkey, gidx);
+    write_record(cur, g, gkey, gidx);
     if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = gkey;
+    // Algorithm 2 after iteration n
+    if (threadIdx.x == 0 && D.tol > 0.0 && n > D.tol_lag &&
+        tolerance_met(gkey, D.hist[n - D.tol_lag], D.tol))
+        B.stop[p] = (double)n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1230,13 +1408,16 @@ __device__ __forceinline__ void rk4_vjp(double mu, double mu1, double h, const d
     for (int d = 0; d < 6; ++d) lam[d] = xb[d] + sb[d];
 }
 
-// Residual angles and their gradients with respect to rho at one
-// observation row; returns false when rho = 0 (no line of sight).
+// Residuals and their gradients with respect to rho at one observation row;
+// returns false when rho = 0 (no line of sight).
 //   d(da)/d rho = (rho_y, -rho_x, 0) / rho_xy^2
 //   d(db)/d rho = (rho_z rho_x / rho_xy, rho_z rho_y / rho_xy, -rho_xy) / |rho|^2
+//   d(dr)/d rho = -rho / |rho|   (range residual dr = observed - |rho|, only
+//                                 when the problem has ranges)
 __device__ __forceinline__ bool residual_and_grad(const double *row, const double S[6],
                                                   double &da, double &db, double ga[3],
-                                                  double gb[3])
+                                                  double gb[3], bool ranged, double &dr,
+                                                  double gr[3])
 {
     const double rx = S[0] - row[TAB_RC + 0];
     const double ry = S[1] - row[TAB_RC + 1];
@@ -1259,6 +1440,13 @@ __device__ __forceinline__ bool residual_and_grad(const double *row, const doubl
     gb[0] = rz * rx / rxy / r2;
     gb[1] = rz * ry / rxy / r2;
     gb[2] = -rxy / r2;
+    if (ranged) {
+        const double r = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+        dr = row[TAB_RANGE] - r;
+        gr[0] = -rx / r;
+        gr[1] = -ry / r;
+        gr[2] = -rz / r;
+    }
     return true;
 }
 
@@ -1272,13 +1460,16 @@ __device__ __forceinline__ void obs_cotangent(const KArgs &A, const double *row,
 #pragma unroll
     for (int d = 0; d < 6; ++d) S[d] = X[d];
     if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, S);
-    double da = 0, db = 0, ga[3], gb[3];
+    double da = 0, db = 0, ga[3], gb[3], dr = 0, gr[3] = {0, 0, 0};
     double sbar[6] = {0, 0, 0, 0, 0, 0};
-    if (residual_and_grad(row, S, da, db, ga, gb)) {
-        const double e = A.w * fma(da, da, db * db);
-        const double gp = (A.mode == 1 ? 1.0 : 2.0 * e) * 2.0 * A.w;
+    const bool ranged = A.wr != 0.0;
+    if (residual_and_grad(row, S, da, db, ga, gb, ranged, dr, gr)) {
+        double e = A.w * fma(da, da, db * db);
+        if (ranged) e = fma(A.wr * dr, dr, e);
+        const double gp = (A.mode == 1 ? 1.0 : 2.0 * e) * 2.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sbar[d] = gp * fma(da, ga[d], db * gb[d]);
+        for (int d = 0; d < 3; ++d)
+            sbar[d] = gp * fma(A.wr * dr, gr[d], A.w * fma(da, ga[d], db * gb[d]));
     } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) sbar[d] = NAN;
@@ -1317,7 +1508,7 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
     double X[6];
     load_state(B.x, B.ld, g, X);
     double J = 0.0;
-    CostAcc acc{0.0, A.w, A.mode};
+    CostAcc acc{0.0, A.w, A.mode, A.wr};
     int32_t k = 0;
     for (int32_t n = 0; n <= S; ++n) {
         if (n < S && n % CKPT == 0 && valid) {
@@ -1434,6 +1625,8 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
     const bool valid = i < D.m;
     const int64_t g = D.off + (valid ? i : D.m - 1);
     const double is = sqrt(A.w);   // 1 / sigma
+    const bool ranged = A.wr != 0.0;
+    const double isr = sqrt(A.wr); // 1 / sigma_range
     double X[6], Phi[36];
     load_state(B.x, B.ld, g, X);
 #pragma unroll
@@ -1455,18 +1648,19 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
             for (int d = 0; d < 36; ++d) SP[d] = Phi[d];
             const double tau = row[TAB_TAU];
             if (tau != 0.0) tangent_step(A.mu, A.mu1, tau, Sx, SP);
-            double da, db, ga[3], gb[3];
-            if (!residual_and_grad(row, Sx, da, db, ga, gb)) {
-                da = db = NAN;
-                ga[0] = ga[1] = ga[2] = gb[0] = gb[1] = gb[2] = NAN;
+            double da, db, ga[3], gb[3], dr = 0, gq[3] = {0, 0, 0};
+            if (!residual_and_grad(row, Sx, da, db, ga, gb, ranged, dr, gq)) {
+                da = db = dr = NAN;
+                ga[0] = ga[1] = ga[2] = gb[0] = gb[1] = gb[2] = gq[0] = gq[1] = gq[2] = NAN;
             }
-            double ja[6], jb[6];
+            double ja[6], jb[6], jr[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 ja[c] = is * fma(ga[0], SP[c], fma(ga[1], SP[6 + c], ga[2] * SP[12 + c]));
                 jb[c] = is * fma(gb[0], SP[c], fma(gb[1], SP[6 + c], gb[2] * SP[12 + c]));
+                jr[c] = isr * fma(gq[0], SP[c], fma(gq[1], SP[6 + c], gq[2] * SP[12 + c]));
             }
-            const double ra = da * is, rb = db * is;
+            const double ra = da * is, rb = db * is, rr = dr * isr;
             c2 = fma(ra, ra, fma(rb, rb, c2));
             int t = 0;
 #pragma unroll
@@ -1474,6 +1668,16 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
                 gr[r] = fma(ja[r], ra, fma(jb[r], rb, gr[r]));
 #pragma unroll
                 for (int c = r; c < 6; ++c, ++t) N[t] = fma(ja[r], ja[c], fma(jb[r], jb[c], N[t]));
+            }
+            if (ranged) {
+                c2 = fma(rr, rr, c2);
+                t = 0;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    gr[r] = fma(jr[r], rr, gr[r]);
+#pragma unroll
+                    for (int c = r; c < 6; ++c, ++t) N[t] = fma(jr[r], jr[c], N[t]);
+                }
             }
             ++k;
         }
@@ -1628,6 +1832,14 @@ hipError_t launch_predict(const KArgs &A, const double *x, int64_t ld, int64_t m
                           double *angles, hipStream_t st)
 {
     hipLaunchKernelGGL(k_predict, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, angles);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_ranges(const KArgs &A, const double *x, int64_t ld, int64_t m,
+                                 double *ranges, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_predict_ranges, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m,
+                       ranges);
     return hipGetLastError();
 }
 

@@ -90,11 +90,51 @@ def test_calls_reject_null_handle_and_bad_shapes():
     assert L.iod_eval_swarm(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
     assert L.iod_propagate(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
     assert L.iod_predict(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
+    assert L.iod_predict_ranges(None, dummy, 64, 64, dummy, None) == iod.IOD_EINVAL
     assert L.iod_destroy(None) == iod.IOD_OK
     assert L.iod_num_obs(None) == iod.IOD_EINVAL
     assert L.iod_swarm_work_len(0) == iod.IOD_EINVAL
     assert L.iod_swarm_work_len(1) > 0
-    assert L.iod_swarm_work_len(65536) == 2 * 1024 * 8 + 16
+    assert L.iod_swarm_work_len(65536) == 2 * 1024 * 8 + 24
     p = iod.pso_params(0.7, 1.5, 1.5, 0, np.zeros(6), np.ones(6))
     assert L.iod_solve(None, C.byref(p), 10, 10, None, None, None) == iod.IOD_EINVAL
     assert L.iod_step(None, None, C.byref(p), 1, None) == iod.IOD_EINVAL
+
+
+def _create_ranged_raw(ranges, sigma_range):
+    L = iod.lib()
+    t = np.array(W.even_times(0.5, 10))
+    ang = np.zeros((10, 2))
+    r = np.array(ranges, dtype=np.float64)
+    h = C.c_void_p()
+    return L.iod_create_ranged(0.0121, iod._dp(np.array(W.C0_CHIEF)), iod._dp(t), iod._dp(ang),
+                               iod._dp(r), 10, 1e-5, sigma_range, None, C.byref(h))
+
+
+@pytest.mark.parametrize("ranges,sigma_range", [
+    ([1e-3] * 10, 0.0), ([1e-3] * 10, -1e-7), ([1e-3] * 10, float("nan")),
+    ([1e-3] * 9 + [-1e-3], 1e-7), ([1e-3] * 9 + [float("inf")], 1e-7),
+])
+def test_create_ranged_rejects_invalid(ranges, sigma_range):
+    assert _create_ranged_raw(ranges, sigma_range) == iod.IOD_EINVAL
+    assert iod.iod_last_error() != ""
+
+
+def test_batch_ranged_needs_sigma_range():
+    L = iod.lib()
+    t = np.array(W.even_times(0.5, 10))
+    off = np.array([0, 10], dtype=np.int64)
+    h = C.c_void_p()
+    rc = L.iod_create_batch_ranged(1, iod._dp(np.array([0.0121])), iod._dp(np.array(W.C0_CHIEF)),
+                                   off.ctypes.data_as(iod._I64), iod._dp(t),
+                                   iod._dp(np.zeros(20)), iod._dp(np.full(10, 1e-3)),
+                                   iod._dp(np.array([1e-5])), None, None, C.byref(h))
+    assert rc == iod.IOD_EINVAL
+
+
+def test_pso_params_layout_matches_header():
+    # omega, eta1, eta2, seed, problem, lo[6], hi[6], flags, tol_lag, tol
+    assert C.sizeof(iod.iod_pso_params) == 8 * 5 + 8 * 12 + 4 + 4 + 8
+    p = iod.pso_params(0.7, 2.05, 2.05, 3, np.zeros(6), np.ones(6), problem=2,
+                       flags=iod.IOD_PSO_CONSTRICTION | iod.IOD_PSO_GRID_INIT, tol=1e-4, tol_lag=7)
+    assert p.flags == 5 and p.tol_lag == 7 and p.tol == 1e-4 and p.problem == 2
