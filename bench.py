@@ -37,6 +37,7 @@ UNIT = "particle·RK4-steps/s"
 FLOP_PER_STEP = 186      # RK4 step: 170 flops + 8 sqrt + 8 div
 FLOP_PER_OBS = 27        # residual and cost: 24 flops + 1 sqrt + 2 atan2
 FLOP_PER_UPDATE = 50     # PSO velocity/position update of one particle
+FLOP_PER_RANGE = 10      # range term: |rho| (5 flops + 1 sqrt), residual, weight and fma
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
 
@@ -64,6 +65,25 @@ def load_traffic():
     return float(kv["hbm_bytes_per_launch"])
 
 
+# The paper's variants beside Algorithm 1 (all off in the default run).
+VARIANTS = ("none", "range", "kappa", "perdim", "grid", "tol")
+
+
+def variant_params(name, iod, wl):
+    """Keyword arguments of pso_params (and omega/eta overrides) for a variant."""
+    kw = dict(omega=wl.omega, eta1=wl.eta1, eta2=wl.eta2, flags=0, tol=0.0, tol_lag=10)
+    if name == "kappa":
+        # the classical constricted swarm: omega = 1, eta1 = eta2 = 2.05 (phi = 4.1)
+        kw.update(omega=1.0, eta1=2.05, eta2=2.05, flags=iod.IOD_PSO_CONSTRICTION)
+    elif name == "perdim":
+        kw.update(flags=iod.IOD_PSO_PER_DIM_R)
+    elif name == "grid":
+        kw.update(flags=iod.IOD_PSO_GRID_INIT)
+    elif name == "tol":
+        kw.update(tol=1e-3, tol_lag=10)   # Algorithm 2 with the listing's lag of 10
+    return kw
+
+
 def make_workload(name):
     from paper_2207_13175_amd import workloads as W
     if name == "c1":
@@ -73,16 +93,24 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def observed_angles(iod, torch, wl):
-    """Truth prediction by the library (placeholder angles) plus the seeded noise."""
+def observed_angles(iod, torch, wl, with_ranges=False):
+    """Truth prediction by the library (placeholder angles) plus the seeded
+    noise; with_ranges: also (observed ranges, sigma_range)."""
+    from paper_2207_13175_amd import workloads as W
     h0 = iod.iod_create(wl.mu, wl.chief, wl.t, np.zeros((wl.K, 2)), wl.sigma, h=wl.h)
     x = torch.zeros((6, 64), dtype=torch.float64, device="cuda")
     x[:, 0] = torch.from_numpy(wl.truth).cuda()
     ang = torch.zeros((wl.K, 2, 64), dtype=torch.float64, device="cuda")
     iod.iod_predict(h0, x, 1, ang)
+    rng = torch.zeros((wl.K, 64), dtype=torch.float64, device="cuda")
+    iod.iod_predict_ranges(h0, x, 1, rng)
     torch.cuda.synchronize()
     iod.iod_destroy(h0)
-    return ang[:, :, 0].cpu().numpy() + wl.noise
+    obs = ang[:, :, 0].cpu().numpy() + wl.noise
+    if not with_ranges:
+        return obs
+    ranges = rng[:, 0].cpu().numpy() + W.range_noise(wl.pso_seed, wl.K, W.SIGMA_RANGE)
+    return obs, ranges, W.SIGMA_RANGE
 
 
 def cpu_baseline(wl, obs, target_s):
@@ -108,16 +136,22 @@ def cpu_baseline(wl, obs, target_s):
                       f"{el:.1f} s wall"}
 
 
-def batch_with_observations(iod, wl):
-    """Batch whose observed angles are the library's prediction for each
-    problem's true deputy plus the seeded noise."""
+def batch_with_observations(iod, wl, ranges=False):
+    """Batch whose observed angles (and, with ranges, ranges) are the
+    library's prediction for each problem's true deputy plus seeded noise."""
+    from paper_2207_13175_amd import workloads as W
     zeros = [np.zeros((len(t), 2)) for t in wl.t]
     b0 = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, zeros, [wl.sigma] * wl.P, h=wl.h)
     pred = iod.iod_batch_predict(b0, wl.truth)
+    pr = iod.iod_batch_predict_ranges(b0, wl.truth) if ranges else None
     iod.iod_batch_destroy(b0)
     obs = [pred[p] + wl.noise[p] for p in range(wl.P)]
     print(f"# observations simulated for {wl.P} problems", file=sys.stderr, flush=True)
-    return iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    if not ranges:
+        return iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    rg = [pr[p] + W.range_noise(1000 + p, len(wl.t[p]), W.SIGMA_RANGE) for p in range(wl.P)]
+    return iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h,
+                                obs_ranges=rg, sigma_range=[W.SIGMA_RANGE] * wl.P)
 
 
 def run_refine(args, iod, torch):
@@ -181,18 +215,23 @@ def run_batch(args, iod, torch, top_k=0):
     wl = W.c2(0)
     if args.iters is not None:
         wl.n_iter = args.iters
-    b = batch_with_observations(iod, wl)
-    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+    b = batch_with_observations(iod, wl, ranges=args.variant == "range")
+    vk = variant_params(args.variant, iod, wl)
+    params = [iod.pso_params(vk["omega"], vk["eta1"], vk["eta2"], wl.pso_seed, wl.lo[p], wl.hi[p],
+                             problem=p, flags=vk["flags"], tol=vk["tol"], tol_lag=vk["tol_lag"])
               for p in range(wl.P)]
     cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
     print(f"# autotuned: block {cfg.block} order {cfg.order} graph {cfg.graph}", file=sys.stderr,
           flush=True)
     steps = iod.iod_batch_steps(b)
 
+    want_hist = args.variant == "tol"
+
     def solve():
         if top_k:
-            return iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=top_k, history=False)
-        return iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+            return iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=top_k,
+                                             history=want_hist)
+        return iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=want_hist)
 
     for _ in range(args.warmup):
         solve()
@@ -200,10 +239,15 @@ def run_batch(args, iod, torch, top_k=0):
     iter_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g, J, _ = solve()
+        g, J, hist = solve()
         iter_ms.append(iod.iod_batch_last_iter_ms(b))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # iterations each problem ran (fewer than n_iter where Algorithm 2 ended it)
+    if hist is not None:
+        n_run = np.array([int(np.max(np.flatnonzero(~np.isnan(hp)))) for hp in hist])
+    else:
+        n_run = np.full(wl.P, wl.n_iter)
     compare = None
     if top_k:
         # the FP64 swarm on the same batch, untimed, for the error statement
@@ -217,9 +261,13 @@ def run_batch(args, iod, torch, top_k=0):
                    "cost_ratio_vs_fp64_q10_50_90": q(ratio),
                    "pos_err_mixed_q10_50_90": q(emx), "pos_err_fp64_q10_50_90": q(e64),
                    "same_best_state": int(np.sum(dstate == 0))}
-    ps_per_solve = int(wl.n_iter) * int(np.sum(wl.m * steps))
-    flop_launch = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
+    ps_per_solve = int(np.sum(n_run * wl.m * steps))
+    per_obs = FLOP_PER_OBS + (FLOP_PER_RANGE if args.variant == "range" else 0)
+    flop_launch = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * per_obs + FLOP_PER_UPDATE)))
     launch_s = float(np.mean(iter_ms)) * 1e-3
+    # with Algorithm 2 the mean launch also holds the stopped problems' empty
+    # iterations: scale the work by the fraction of problem-iterations run
+    flop_launch *= float(np.sum(n_run * wl.m * steps)) / float(np.sum(wl.n_iter * wl.m * steps))
     achieved = flop_launch / launch_s / 1e12
     peak = PEAK_FP32_TFLOPS if top_k else PEAK_FP64_TFLOPS
     err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
@@ -228,7 +276,10 @@ def run_batch(args, iod, torch, top_k=0):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if top_k else "f64", "data": "synthetic",
-        "config": {"workload": wl.name + (f"_mixed_top{top_k}" if top_k else ""),
+        "config": {"workload": wl.name + (f"_mixed_top{top_k}" if top_k else "")
+                               + ("" if args.variant == "none" else "_" + args.variant),
+                   "variant": args.variant,
+                   "iterations_run_q10_50_90": [float(np.quantile(n_run, v)) for v in (0.1, 0.5, 0.9)],
                    "mixed_vs_fp64": compare, "problems": wl.P, "particles": int(wl.m.sum()),
                    "iterations": wl.n_iter, "obs_range": [int(wl.K.min()), int(wl.K.max())],
                    "steps_range": [int(steps.min()), int(steps.max())], "h": wl.h,
@@ -258,6 +309,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
+    ap.add_argument("--variant", default="none", choices=VARIANTS,
+                    help="one of the paper's variants beside Algorithm 1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -287,11 +340,17 @@ def main():
     wl = make_workload(args.workload)
     if args.iters is not None:
         wl.n_iter = args.iters
-    obs = observed_angles(iod, torch, wl)
-    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    if args.variant == "range":
+        obs, ranges, sigma_r = observed_angles(iod, torch, wl, with_ranges=True)
+        h = iod.iod_create_ranged(wl.mu, wl.chief, wl.t, obs, ranges, wl.sigma, sigma_r, h=wl.h)
+    else:
+        obs = observed_angles(iod, torch, wl)
+        h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
     ns, _ = iod.iod_schedule(wl.t, wl.h)
     steps_per_eval = int(ns[-1])
-    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo, wl.hi)
+    vk = variant_params(args.variant, iod, wl)
+    params = iod.pso_params(vk["omega"], vk["eta1"], vk["eta2"], wl.pso_seed, wl.lo, wl.hi,
+                            flags=vk["flags"], tol=vk["tol"], tol_lag=vk["tol_lag"])
     sw = iod.Swarm(wl.m, device="cuda", hist_len=wl.n_iter + 1)
     stream = torch.cuda.current_stream()
 
@@ -328,14 +387,20 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    launch_ms = [e0.elapsed_time(e1) for row in evs for (e0, e1) in row]
+    # iterations actually run (all of them unless Algorithm 2 ended the run;
+    # the history is NaN after its stop and the later launches do no work)
+    hist = sw.hist.cpu().numpy()
+    n_run = int(np.max(np.flatnonzero(~np.isnan(hist))))
+    launch_ms = [e0.elapsed_time(e1) for row in evs for (e0, e1) in row[:n_run]]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     # average algorithmic work of one iteration-kernel launch: every launch
     # updates m particles, all but the first iteration also evaluate them
     flop_eval = steps_per_eval * FLOP_PER_STEP + wl.K * FLOP_PER_OBS
-    flop_launch = wl.m * ((wl.n_iter - 1) / wl.n_iter * flop_eval + FLOP_PER_UPDATE)
+    flop_launch = wl.m * ((n_run - 1) / n_run * flop_eval + FLOP_PER_UPDATE)
+    if args.variant == "range":
+        flop_launch += wl.m * (n_run - 1) / n_run * wl.K * FLOP_PER_RANGE
     achieved = flop_launch / avg_launch_s / 1e12
-    ps_per_solve = wl.particle_steps(steps_per_eval)
+    ps_per_solve = n_run * wl.m * steps_per_eval
     value = args.steps * ps_per_solve / elapsed
 
     out = {
@@ -343,7 +408,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "particles": wl.m, "iterations": wl.n_iter,
+        "config": {"workload": wl.name + ("" if args.variant == "none" else "_" + args.variant),
+                   "variant": args.variant, "iterations_run": n_run,
+                   "particles": wl.m, "iterations": wl.n_iter,
                    "observations": wl.K, "arc_tu": float(wl.t[-1]), "h": wl.h,
                    "rk4_steps_per_eval": steps_per_eval,
                    "particle_steps_per_solve": ps_per_solve,

@@ -196,3 +196,13 @@ def c4(seed: int = 0, P: int = 4096, n_iter: int = 100, m: int = 2048) -> BatchW
     wl.name = f"c4_P{P}_m{m}_N{n_iter}"
     wl.m = np.full(P, m, dtype=np.int64)
     return wl
+
+
+def range_noise(seed: int, K: int, sigma_range: float) -> np.ndarray:
+    """[K] N(0, sigma_range^2) draws for range measurements (LU)."""
+    rng = np.random.default_rng([seed, 5])
+    return rng.standard_normal(K) * sigma_range
+
+
+# Range noise used with the range-measurement variant: 1e-7 LU (about 40 m).
+SIGMA_RANGE = 1e-7
