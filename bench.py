@@ -42,12 +42,17 @@ PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_13175_amd", "csrc", "iod_kernels.hip")
+# sources the FP64 iteration kernel is built from
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_13175_amd", "csrc", f)
+               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():

@@ -15,7 +15,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libiod.so")
-SOURCES = [os.path.join(CSRC, "iod_kernels.hip"), os.path.join(CSRC, "iod_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("iod_kernels.hip", "iod_mixed.hip", "iod_sens.hip", "iod_api.hip")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

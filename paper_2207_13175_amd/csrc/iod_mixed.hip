@@ -1,0 +1,453 @@
+// iod_mixed.hip -- gfx950 kernels of libiod's mixed-precision swarm: FP32
+// RK4 propagation with a Kahan-compensated state ranks the particles; per
+// problem the top-k personal bests are selected and re-evaluated in FP64,
+// and the global best of Algorithm 1 (Zuehlke et al., AAS 22-770) is decided
+// on those FP64 costs. A systems variant: the paper works in double
+// precision throughout.
+#include "iod_device.h"
+
+namespace iodk {
+
+// ---------------------------------------------------------------------------
+// Mixed precision: FP32 propagation with a Kahan-compensated state, used to
+// rank particles; FP64 re-evaluation of the best candidates decides the
+// global best.
+// ---------------------------------------------------------------------------
+
+// FP32 right-hand side. 1/r^3 comes from the hardware reciprocal square root
+// (about 1 ulp), cubed: c_j = mu_j rsq(r_j^2)^3.
+__device__ __forceinline__ void rhs32(float mu, float mu1, const float s[6], float f[6])
+{
+    const float x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4];
+    const float d1 = x + mu;
+    const float d2 = x - mu1;
+    const float q = fmaf(z, z, y * y);
+    const float y1 = __builtin_amdgcn_rsqf(fmaf(d1, d1, q));
+    const float y2 = __builtin_amdgcn_rsqf(fmaf(d2, d2, q));
+    const float c1 = mu1 * (y1 * y1 * y1);
+    const float c2 = mu * (y2 * y2 * y2);
+    const float cs = c1 + c2;
+    f[0] = s[3];
+    f[1] = s[4];
+    f[2] = s[5];
+    f[3] = fmaf(-c2, d2, fmaf(-c1, d1, fmaf(2.0f, vy, x)));
+    f[4] = fmaf(-cs, y, fmaf(-2.0f, vx, y));
+    f[5] = -(cs * z);
+}
+
+// FP32 RK4 step. The stages see X; the increment h/6 (k1 + 2k2 + 2k3 + k4)
+// is added with Kahan compensation, C holding minus the lost low part, so
+// the accumulated state is X - C.
+__device__ __forceinline__ void rk4_32(float mu, float mu1, float h, float h2, float h6,
+                                       float X[6], float C[6])
+{
+    float k[6], a[6], s[6];
+    rhs32(mu, mu1, X, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = k[d];
+        s[d] = fmaf(h2, k[d], X[d]);
+    }
+    rhs32(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fmaf(2.0f, k[d], a[d]);
+        s[d] = fmaf(h2, k[d], X[d]);
+    }
+    rhs32(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fmaf(2.0f, k[d], a[d]);
+        s[d] = fmaf(h, k[d], X[d]);
+    }
+    rhs32(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = a[d] + k[d];
+        const float yv = fmaf(h6, a[d], -C[d]);
+        const float t = X[d] + yv;
+        C[d] = (t - X[d]) - yv;
+        X[d] = t;
+    }
+}
+
+// FP32 walk of the schedule; obs(row, X, C) sees the compensated pair.
+template <class Obs>
+__device__ __forceinline__ void walk32(const KArgs &A, float X[6], float C[6], double *lds,
+                                       int32_t *lds_ns, Obs &obs)
+{
+    const float mu = (float)A.mu, mu1 = (float)A.mu1;
+    const float h = (float)A.h, h2 = 0.5f * h, h6 = h / 6.0f;
+    int32_t step = 0;
+    for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
+        const int32_t nk = min(OBS_CHUNK, A.K - k0);
+        __syncthreads();
+        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
+            lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
+        for (int32_t j = threadIdx.x; j < nk; j += blockDim.x) lds_ns[j] = A.ns[k0 + j];
+        __syncthreads();
+        for (int32_t kk = 0; kk < nk; ++kk) {
+            const double *row = lds + kk * TAB_W;
+            const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
+            for (; step < target; ++step) rk4_32(mu, mu1, h, h2, h6, X, C);
+            const float tau = (float)row[TAB_TAU];
+            float S[6], SC[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                S[d] = X[d];
+                SC[d] = C[d];
+            }
+            if (tau != 0.0f) rk4_32(mu, mu1, tau, 0.5f * tau, tau / 6.0f, S, SC);
+            obs(row, S, SC);
+        }
+    }
+}
+
+// FP32 residual cost. rho = (X - C) - r_chief is formed as
+// (X - rc_hi) - (C + rc_lo) with the chief split into an FP32 pair, so the
+// small chief-to-deputy offset keeps the precision of the compensated state.
+struct CostAcc32 {
+    double J;
+    float w;
+    int32_t mode;
+    float wr;   // range weight, 0 = angles only
+    __device__ __forceinline__ void operator()(const double *row, const float S[6], const float C[6])
+    {
+        float r[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double rc = row[TAB_RC + d];
+            const float hi = (float)rc;
+            const float lo = (float)(rc - (double)hi);
+            r[d] = (S[d] - hi) - (C[d] + lo);
+        }
+        const float sa = (float)row[TAB_SA], ca = (float)row[TAB_CA];
+        const float sb = (float)row[TAB_SB], cb = (float)row[TAB_CB];
+        float e;
+        if (r[0] == 0.0f && r[1] == 0.0f && r[2] == 0.0f) {
+            e = INFINITY;
+        } else {
+            const float rxy = sqrtf(fmaf(r[0], r[0], r[1] * r[1]));
+            float na, nd;
+            if (rxy == 0.0f) {
+                na = sa;
+                nd = ca;
+            } else {
+                na = fmaf(sa, r[0], -(ca * r[1]));
+                nd = fmaf(ca, r[0], sa * r[1]);
+            }
+            const float da = atan2f(na, nd);
+            const float db = atan2f(fmaf(sb, rxy, -(cb * r[2])), fmaf(cb, rxy, sb * r[2]));
+            e = w * fmaf(da, da, db * db);
+            if (wr != 0.0f) {
+                const float dr = (float)row[TAB_RANGE] - sqrtf(fmaf(r[0], r[0], fmaf(r[1], r[1], r[2] * r[2])));
+                e = fmaf(wr * dr, dr, e);
+            }
+        }
+        const double ed = e;
+        J = (mode == 1) ? J + ed : fma(ed, ed, J);
+    }
+};
+
+__device__ __forceinline__ double eval_cost32(const KArgs &A, const double x0[6], double *lds,
+                                              int32_t *lds_ns)
+{
+    float X[6], C[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        X[d] = (float)x0[d];
+        C[d] = -(float)(x0[d] - (double)X[d]);   // X - C carries x0 to ~2^-48
+    }
+    CostAcc32 acc{0.0, (float)A.w, A.mode, (float)A.wr};
+    walk32(A, X, C, lds, lds_ns, acc);
+    return acc.J;
+}
+
+struct StoreStates32 {
+    double *out;
+    int64_t ld, i;
+    int32_t k;
+    bool valid;
+    __device__ __forceinline__ void operator()(const double *, const float S[6], const float C[6])
+    {
+        if (valid) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+                out[((int64_t)k * 6 + d) * ld + i] = (double)S[d] - (double)C[d];
+        }
+        ++k;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_propagate32(KArgs A, const double *__restrict__ x,
+                                                     int64_t ld, int64_t m,
+                                                     double *__restrict__ states)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < m;
+    const int64_t j = valid ? i : m - 1;
+    float X[6], C[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const double v = x[d * ld + j];
+        X[d] = (float)v;
+        C[d] = -(float)(v - (double)X[d]);
+    }
+    StoreStates32 obs{states, ld, i, 0, valid};
+    walk32(A, X, C, lds, lds_ns, obs);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eval32(ProbDesc d0, SwarmArrays B)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    int64_t p, tile;
+    const ProbDesc &D = locate<false>(d0, B, p, tile);
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    double X[6];
+    load_state(B.x, B.ld, D.off + (valid ? i : D.m - 1), X);
+    const double J = eval_cost32(D.k, X, lds, lds_ns);
+    if (valid) B.cost[D.off + i] = J;
+}
+
+// Mixed-precision initialisation: as k_swarm_init with FP32 ranking costs;
+// no argmin slots (the global best comes from the FP64 re-evaluation).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    int64_t p, tile;
+    const ProbDesc &D = locate<false>(d0, B, p, tile);
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t j = valid ? i : D.m - 1;
+    double X[6];
+    init_state(D, j, X);
+    const double J = eval_cost32(D.k, X, lds, lds_ns);
+    const int64_t ld = B.ld, g = D.off + i;
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            B.x[d * ld + g] = X[d];
+            B.v[d * ld + g] = 0.0;
+            B.p[d * ld + g] = X[d];
+        }
+        B.jp[g] = J;
+        B.cost[g] = J;
+    }
+    if (tile == 0 && threadIdx.x < REC)
+        B.recs[(B.nprob + p) * REC + threadIdx.x] = threadIdx.x == 0 ? INFINITY : threadIdx.x == 1 ? -1.0 : 0.0;
+    if (tile == 0 && threadIdx.x == 0) B.stop[p] = -1.0;
+}
+
+// Mixed-precision iteration n >= 1: FP32 evaluation and personal best, then
+// the FP64 swarm update towards the FP64-decided global best G_{n-1}.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, int64_t n)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    int64_t p, tile;
+    const ProbDesc &D = locate<false>(d0, B, p, tile);
+    if (B.stop[p] >= 0.0) return;   // ended by Algorithm 2
+    const double *rec = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
+    double g[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) g[d] = rec[2 + d];
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t j = valid ? i : D.m - 1;
+    const int64_t ld = B.ld, gj = D.off + j, gi = D.off + i;
+    double X[6], V[6], Pb[6];
+    load_state(B.x, ld, gj, X);
+    load_state(B.v, ld, gj, V);
+    load_state(B.p, ld, gj, Pb);
+    double jp = B.jp[gj];
+    const double J = n >= 2 ? eval_cost32(D.k, X, lds, lds_ns) : B.cost[gj];
+    const bool better = cost_key(J) < cost_key(jp);
+    if (better) {
+        jp = J;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Pb[d] = X[d];
+    }
+    pso_update(D, n, j, X, V, Pb, g);
+    if (valid) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            B.x[d * ld + gi] = X[d];
+            B.v[d * ld + gi] = V[d];
+        }
+        if (n >= 2) B.cost[gi] = J;
+        if (better) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) B.p[d * ld + gi] = Pb[d];
+            B.jp[gi] = jp;
+        }
+    }
+}
+
+// Bitonic sort of 2 * blockDim (key, index) pairs in LDS, lexicographic.
+__device__ __forceinline__ void bitonic_sort(double *key, double *idx, int n)
+{
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const bool swap = up ? lex_less(key[hi], idx[hi], key[lo], idx[lo])
+                                     : lex_less(key[lo], idx[lo], key[hi], idx[hi]);
+                if (swap) {
+                    const double tk = key[lo], ti = idx[lo];
+                    key[lo] = key[hi];
+                    idx[lo] = idx[hi];
+                    key[hi] = tk;
+                    idx[hi] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Per problem (one workgroup of TOPK_BS threads): the top_k particles with
+// the smallest (key(key[i]), i), in order, into out[p][0..top_k). Slots
+// beyond m are -1. top_k <= TOPK_BS.
+constexpr int TOPK_BS = 256;
+
+__global__ __launch_bounds__(TOPK_BS) void k_topk(SwarmArrays B, const double *__restrict__ keys,
+                                                  int32_t top_k, int32_t *__restrict__ out)
+{
+    __shared__ double sk[2 * TOPK_BS], si[2 * TOPK_BS];
+    const int64_t p = blockIdx.x;
+    const ProbDesc &D = B.desc[p];
+    const int t = threadIdx.x;
+    // running best list in [0, TOPK_BS), new chunk in [TOPK_BS, 2 TOPK_BS)
+    sk[t] = INFINITY;
+    si[t] = INFINITY;
+    for (int64_t c0 = 0; c0 < D.m; c0 += TOPK_BS) {
+        const int64_t i = c0 + t;
+        sk[TOPK_BS + t] = i < D.m ? cost_key(keys[D.off + i]) : INFINITY;
+        si[TOPK_BS + t] = i < D.m ? (double)i : INFINITY;
+        __syncthreads();
+        bitonic_sort(sk, si, 2 * TOPK_BS);
+    }
+    if (t < top_k) out[p * top_k + t] = si[t] < (double)D.m ? (int32_t)si[t] : -1;
+}
+
+// Per problem (one workgroup of 64 threads): FP64 costs of the personal
+// bests of the selected candidates; the lowest (cost, index) replaces the
+// record of iteration n-1 if the record is empty or the cost is strictly
+// lower. Writes record n and hist[n].
+__global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *__restrict__ cand,
+                                                 int32_t top_k, int64_t n)
+{
+    __shared__ double lds[OBS_CHUNK * TAB_W];
+    __shared__ int32_t lds_ns[OBS_CHUNK];
+    __shared__ double red[2];
+    __shared__ double wst[6];
+    const int64_t p = blockIdx.x;
+    const ProbDesc &D = B.desc[p];
+    const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
+    double *cur = B.recs + ((n & 1) * B.nprob + p) * REC;
+    if (B.stop[p] >= 0.0) {
+        // ended by Algorithm 2: carry the final record forward
+        if (threadIdx.x < REC) cur[threadIdx.x] = prev[threadIdx.x];
+        if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = NAN;
+        return;
+    }
+    double bkey = INFINITY, bidx = INFINITY, bst[6] = {0, 0, 0, 0, 0, 0};
+    for (int c0 = 0; c0 < top_k; c0 += 64) {
+        const int c = c0 + (int)threadIdx.x;
+        const int32_t i = c < top_k ? cand[p * top_k + c] : -1;
+        const bool valid = i >= 0;
+        double X[6];
+        load_state(B.p, B.ld, D.off + (valid ? i : 0), X);
+        const double J = eval_cost(D.k, X, lds, lds_ns);
+        const double k = valid ? cost_key(J) : INFINITY, ix = valid ? (double)i : INFINITY;
+        if (lex_less(k, ix, bkey, bidx)) {
+            bkey = k;
+            bidx = ix;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) bst[d] = X[d];
+        }
+    }
+    double key = bkey, idx = bidx;
+    block_argmin(key, idx, red);
+    if (bidx == idx && bkey == key) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) wst[d] = bst[d];
+    }
+    __syncthreads();
+    double g[6], gkey, gidx;
+    if (idx < INFINITY && (prev[1] < 0.0 || key < prev[0])) {
+        gkey = key;
+        gidx = idx;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = wst[d];
+    } else {
+        gkey = prev[0];
+        gidx = prev[1];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) g[d] = prev[2 + d];
+    }
+    write_record(cur, g, gkey, gidx);
+    if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = gkey;
+    // Algorithm 2 after iteration n
+    if (threadIdx.x == 0 && D.tol > 0.0 && n > D.tol_lag &&
+        tolerance_met(gkey, D.hist[n - D.tol_lag], D.tol))
+        B.stop[p] = (double)n;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+
+hipError_t launch_propagate32(const KArgs &A, const double *x, int64_t ld, int64_t m,
+                              double *states, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_propagate32, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, states);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval32(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                         hipStream_t st)
+{
+    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_eval32<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                             hipStream_t st)
+{
+    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_init<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                             int64_t n, hipStream_t st)
+{
+    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_iter<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const SwarmArrays &B, const double *keys, int32_t top_k, int32_t *out,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)B.nprob), dim3(TOPK_BS), 0, st, B, keys, top_k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reeval64(const SwarmArrays &B, const int32_t *cand, int32_t top_k, int64_t n,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reeval64, dim3((unsigned)B.nprob), dim3(64), 0, st, B, cand, top_k, n);
+    return hipGetLastError();
+}
+
+}  // namespace iodk

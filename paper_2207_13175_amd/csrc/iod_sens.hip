@@ -1,0 +1,628 @@
+// iod_sens.hip -- gfx950 kernels of libiod's sensitivities and local
+// refinement: the discrete adjoint of the RK4 propagation and the residual
+// cost (cost gradient), the forward tangent (state transition matrix) for
+// the Gauss-Newton normal equations, and the damped Gauss-Newton step and
+// acceptance that refine the swarm's best (in place of the paper's
+// Levenberg-Marquardt Local Minimization, eqs. non:linear:lsq and
+// nonlinlsq:cost).
+#include "iod_device.h"
+
+namespace iodk {
+
+// ---------------------------------------------------------------------------
+// Sensitivities: discrete adjoint (reverse sweep) and forward tangent of the
+// RK4 map, for the cost gradient and the Gauss-Newton polish that refines
+// the swarm's best (the paper's Local Minimization step).
+// ---------------------------------------------------------------------------
+
+// Gravity-plus-centrifugal block of the Jacobian at s, in factored form:
+// d a/d r = diag(1, 1, 0) - cs I + e1 p1 p1^T + e2 p2 p2^T with
+// p_j = (x - x_j, y, z), cs = c1 + c2, e_j = 3 c_j / r_j^2.
+struct JacData {
+    double cs, e1, e2, d1, d2, y, z;
+};
+
+__device__ __forceinline__ JacData jac_data(double mu, double mu1, const double s[6])
+{
+    JacData J;
+    J.y = s[1];
+    J.z = s[2];
+    J.d1 = s[0] + mu;
+    J.d2 = s[0] - mu1;
+    const double q = fma(J.z, J.z, J.y * J.y);
+    const double r1s = fma(J.d1, J.d1, q), r2s = fma(J.d2, J.d2, q);
+    const double c1 = mu1 / (r1s * sqrt(r1s)), c2 = mu / (r2s * sqrt(r2s));
+    J.cs = c1 + c2;
+    J.e1 = 3.0 * c1 / r1s;
+    J.e2 = 3.0 * c2 / r2s;
+    return J;
+}
+
+// G u for the symmetric gravity block.
+__device__ __forceinline__ void gmul(const JacData &J, const double u[3], double out[3])
+{
+    const double p1 = fma(J.d1, u[0], fma(J.y, u[1], J.z * u[2]));
+    const double p2 = fma(J.d2, u[0], fma(J.y, u[1], J.z * u[2]));
+    const double a1 = J.e1 * p1, a2 = J.e2 * p2, a12 = a1 + a2;
+    out[0] = fma(a1, J.d1, fma(a2, J.d2, u[0] - J.cs * u[0]));
+    out[1] = fma(a12, J.y, u[1] - J.cs * u[1]);
+    out[2] = fma(a12, J.z, -J.cs * u[2]);
+}
+
+// A(s) u (tangent) and A(s)^T v (cotangent); A = [[0, I], [G, W]], W the
+// Coriolis block [[0, 2, 0], [-2, 0, 0], [0, 0, 0]].
+__device__ __forceinline__ void amul(const JacData &J, const double u[6], double out[6])
+{
+    double g[3];
+    gmul(J, u, g);
+    out[0] = u[3];
+    out[1] = u[4];
+    out[2] = u[5];
+    out[3] = fma(2.0, u[4], g[0]);
+    out[4] = fma(-2.0, u[3], g[1]);
+    out[5] = g[2];
+}
+
+__device__ __forceinline__ void atmul(const JacData &J, const double v[6], double out[6])
+{
+    double g[3];
+    gmul(J, v + 3, g);
+    out[0] = g[0];
+    out[1] = g[1];
+    out[2] = g[2];
+    out[3] = fma(-2.0, v[4], v[0]);
+    out[4] = fma(2.0, v[3], v[1]);
+    out[5] = v[2];
+}
+
+// Stage inputs of one RK4 step from X (the IEEE path, bit-identical to the
+// propagation), and optionally the stepped state.
+__device__ __forceinline__ void rk4_stages(double mu, double mu1, double h, double h2, double h6,
+                                           const double X[6], double s2[6], double s3[6],
+                                           double s4[6], double *Y)
+{
+    double k[6], a[6];
+    rhs<false>(mu, mu1, X, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = k[d];
+        s2[d] = fma(h2, k[d], X[d]);
+    }
+    rhs<false>(mu, mu1, s2, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s3[d] = fma(h2, k[d], X[d]);
+    }
+    rhs<false>(mu, mu1, s3, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s4[d] = fma(h, k[d], X[d]);
+    }
+    if (Y) {
+        rhs<false>(mu, mu1, s4, k);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Y[d] = fma(h6, a[d] + k[d], X[d]);
+    }
+}
+
+// Reverse (transposed tangent) of one RK4 step taken from X: lam <- (dX'/dX)^T lam.
+// X' = X + h/6 (k1 + 2 k2 + 2 k3 + k4), s2 = X + h/2 k1, s3 = X + h/2 k2, s4 = X + h k3.
+__device__ __forceinline__ void rk4_vjp(double mu, double mu1, double h, const double X[6],
+                                        double lam[6])
+{
+    const double h2 = 0.5 * h, h6 = h / 6.0;
+    double s2[6], s3[6], s4[6];
+    rk4_stages(mu, mu1, h, h2, h6, X, s2, s3, s4, nullptr);
+    double kb[6], sb[6], xb[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) kb[d] = h6 * lam[d];
+    atmul(jac_data(mu, mu1, s4), kb, sb);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        xb[d] = lam[d] + sb[d];
+        kb[d] = fma(2.0 * h6, lam[d], h * sb[d]);
+    }
+    atmul(jac_data(mu, mu1, s3), kb, sb);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        xb[d] += sb[d];
+        kb[d] = fma(2.0 * h6, lam[d], h2 * sb[d]);
+    }
+    atmul(jac_data(mu, mu1, s2), kb, sb);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        xb[d] += sb[d];
+        kb[d] = fma(h6, lam[d], h2 * sb[d]);
+    }
+    atmul(jac_data(mu, mu1, X), kb, sb);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) lam[d] = xb[d] + sb[d];
+}
+
+// Residuals and their gradients with respect to rho at one observation row;
+// returns false when rho = 0 (no line of sight).
+//   d(da)/d rho = (rho_y, -rho_x, 0) / rho_xy^2
+//   d(db)/d rho = (rho_z rho_x / rho_xy, rho_z rho_y / rho_xy, -rho_xy) / |rho|^2
+//   d(dr)/d rho = -rho / |rho|   (range residual dr = observed - |rho|, only
+//                                 when the problem has ranges)
+__device__ __forceinline__ bool residual_and_grad(const double *row, const double S[6],
+                                                  double &da, double &db, double ga[3],
+                                                  double gb[3], bool ranged, double &dr,
+                                                  double gr[3])
+{
+    const double rx = S[0] - row[TAB_RC + 0];
+    const double ry = S[1] - row[TAB_RC + 1];
+    const double rz = S[2] - row[TAB_RC + 2];
+    if (rx == 0.0 && ry == 0.0 && rz == 0.0) return false;
+    const double sa = row[TAB_SA], ca = row[TAB_CA], sb = row[TAB_SB], cb = row[TAB_CB];
+    const double rxy2 = fma(rx, rx, ry * ry);
+    const double rxy = sqrt(rxy2);
+    double na = sa, nd = ca;
+    if (rxy != 0.0) {
+        na = fma(sa, rx, -(ca * ry));
+        nd = fma(ca, rx, sa * ry);
+    }
+    da = atan2(na, nd);
+    db = atan2(fma(sb, rxy, -(cb * rz)), fma(cb, rxy, sb * rz));
+    const double r2 = fma(rz, rz, rxy2);
+    ga[0] = ry / rxy2;
+    ga[1] = -rx / rxy2;
+    ga[2] = 0.0;
+    gb[0] = rz * rx / rxy / r2;
+    gb[1] = rz * ry / rxy / r2;
+    gb[2] = -rxy / r2;
+    if (ranged) {
+        const double r = sqrt(fma(rx, rx, fma(ry, ry, rz * rz)));
+        dr = row[TAB_RANGE] - r;
+        gr[0] = -rx / r;
+        gr[1] = -ry / r;
+        gr[2] = -rz / r;
+    }
+    return true;
+}
+
+// Cotangent of observation k's cost term with respect to the state the
+// observation is taken from (X on the grid; a partial step tau is reversed).
+__device__ __forceinline__ void obs_cotangent(const KArgs &A, const double *row, const double X[6],
+                                              double add[6])
+{
+    const double tau = row[TAB_TAU];
+    double S[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S[d] = X[d];
+    if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, S);
+    double da = 0, db = 0, ga[3], gb[3], dr = 0, gr[3] = {0, 0, 0};
+    double sbar[6] = {0, 0, 0, 0, 0, 0};
+    const bool ranged = A.wr != 0.0;
+    if (residual_and_grad(row, S, da, db, ga, gb, ranged, dr, gr)) {
+        double e = A.w * fma(da, da, db * db);
+        if (ranged) e = fma(A.wr * dr, dr, e);
+        const double gp = (A.mode == 1 ? 1.0 : 2.0 * e) * 2.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            sbar[d] = gp * fma(A.wr * dr, gr[d], A.w * fma(da, ga[d], db * gb[d]));
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sbar[d] = NAN;
+    }
+    if (tau != 0.0) rk4_vjp(A.mu, A.mu1, tau, X, sbar);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) add[d] = sbar[d];
+}
+
+constexpr int CKPT = 64;   // steps between adjoint checkpoints
+
+// Cost and its gradient by the discrete adjoint. Forward: the certified
+// propagation and cost (same bits as k_eval), checkpoints X_{64 j}. Reverse:
+// per 64-step segment, recompute the states from the checkpoint into
+// scratch, then sweep back applying the transposed RK4 step and adding each
+// observation's cotangent at its grid index. Scratch per lane (column g of
+// a [rows][6][wld] array): rows [0, nseg) checkpoints, [nseg, nseg + 64)
+// segment states. mode >= 0 overrides the cost mode.
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double *__restrict__ grad,
+                                             double *__restrict__ work, int64_t wld, int32_t mode)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    KArgs A = D.k;
+    if (mode >= 0) A.mode = mode;
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t g = D.off + (valid ? i : D.m - 1);
+    const int32_t S = A.ns[A.K - 1];
+    const int32_t nseg = (S + CKPT - 1) / CKPT;
+    // private scratch column: invalid lanes alias the last valid particle's
+    // column but only ever read what they wrote themselves in lockstep
+    double *ck = work;
+    double *seg = work + (int64_t)nseg * 6 * wld;
+    double X[6];
+    load_state(B.x, B.ld, g, X);
+    double J = 0.0;
+    CostAcc acc{0.0, A.w, A.mode, A.wr};
+    int32_t k = 0;
+    for (int32_t n = 0; n <= S; ++n) {
+        if (n < S && n % CKPT == 0 && valid) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) ck[((int64_t)(n / CKPT) * 6 + d) * wld + g] = X[d];
+        }
+        while (k < A.K && A.ns[k] == n) {
+            const double *row = A.tab + (int64_t)k * TAB_W;
+            double Sx[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) Sx[d] = X[d];
+            const double tau = row[TAB_TAU];
+            if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sx);
+            acc(row, Sx);
+            ++k;
+        }
+        if (n < S) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
+    }
+    J = acc.J;
+    // reverse sweep
+    double lam[6] = {0, 0, 0, 0, 0, 0};
+    k = A.K - 1;
+    while (k >= 0 && A.ns[k] == S) {
+        double add[6];
+        obs_cotangent(A, A.tab + (int64_t)k * TAB_W, X, add);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) lam[d] += add[d];
+        --k;
+    }
+    for (int32_t sg = nseg - 1; sg >= 0; --sg) {
+        const int32_t a = sg * CKPT, b = min(a + CKPT, S);
+        double Y[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Y[d] = valid ? ck[((int64_t)sg * 6 + d) * wld + g] : X[d];
+        for (int32_t j = a; j < b; ++j) {
+            if (valid) {
+#pragma unroll
+                for (int d = 0; d < 6; ++d) seg[((int64_t)(j - a) * 6 + d) * wld + g] = Y[d];
+            }
+            if (j + 1 < b) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
+        }
+        for (int32_t j = b - 1; j >= a; --j) {
+            double Xj[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) Xj[d] = valid ? seg[((int64_t)(j - a) * 6 + d) * wld + g] : X[d];
+            rk4_vjp(A.mu, A.mu1, A.h, Xj, lam);
+            while (k >= 0 && A.ns[k] == j) {
+                double add[6];
+                obs_cotangent(A, A.tab + (int64_t)k * TAB_W, Xj, add);
+#pragma unroll
+                for (int d = 0; d < 6; ++d) lam[d] += add[d];
+                --k;
+            }
+        }
+    }
+    if (valid) {
+        B.cost[D.off + i] = J;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) grad[d * B.ld + D.off + i] = lam[d];
+    }
+}
+
+// Forward tangent (6x6 state transition matrix of the discrete RK4 map) and
+// the Gauss-Newton normal equations of the whitened residuals
+// r = (da, db) / sigma: chi2 = sum r^2, N = J^T J (21 packed, row-major
+// upper triangle), jtr = J^T r.
+__device__ __forceinline__ void tangent_step(double mu, double mu1, double h, double X[6],
+                                             double Phi[36])
+{
+    const double h2 = 0.5 * h, h6 = h / 6.0;
+    double s2[6], s3[6], s4[6], Y[6];
+    rk4_stages(mu, mu1, h, h2, h6, X, s2, s3, s4, Y);
+    const JacData J1 = jac_data(mu, mu1, X), J2 = jac_data(mu, mu1, s2);
+    const JacData J3 = jac_data(mu, mu1, s3), J4 = jac_data(mu, mu1, s4);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double u[6], dk[6], acc[6], ds[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) u[d] = Phi[6 * d + c];
+        amul(J1, u, dk);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            acc[d] = dk[d];
+            ds[d] = fma(h2, dk[d], u[d]);
+        }
+        amul(J2, ds, dk);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            acc[d] = fma(2.0, dk[d], acc[d]);
+            ds[d] = fma(h2, dk[d], u[d]);
+        }
+        amul(J3, ds, dk);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            acc[d] = fma(2.0, dk[d], acc[d]);
+            ds[d] = fma(h, dk[d], u[d]);
+        }
+        amul(J4, ds, dk);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Phi[6 * d + c] = fma(h6, acc[d] + dk[d], u[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = Y[d];
+}
+
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, double *__restrict__ chi2,
+                                               double *__restrict__ jtj, double *__restrict__ jtr)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const KArgs &A = D.k;
+    const int64_t i = tile * BS + threadIdx.x;
+    const bool valid = i < D.m;
+    const int64_t g = D.off + (valid ? i : D.m - 1);
+    const double is = sqrt(A.w);   // 1 / sigma
+    const bool ranged = A.wr != 0.0;
+    const double isr = sqrt(A.wr); // 1 / sigma_range
+    double X[6], Phi[36];
+    load_state(B.x, B.ld, g, X);
+#pragma unroll
+    for (int d = 0; d < 36; ++d) Phi[d] = (d % 7 == 0) ? 1.0 : 0.0;
+    double c2 = 0.0, N[21], gr[6];
+#pragma unroll
+    for (int d = 0; d < 21; ++d) N[d] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) gr[d] = 0.0;
+    const int32_t S = A.ns[A.K - 1];
+    int32_t k = 0;
+    for (int32_t n = 0; n <= S; ++n) {
+        while (k < A.K && A.ns[k] == n) {
+            const double *row = A.tab + (int64_t)k * TAB_W;
+            double Sx[6], SP[36];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) Sx[d] = X[d];
+#pragma unroll
+            for (int d = 0; d < 36; ++d) SP[d] = Phi[d];
+            const double tau = row[TAB_TAU];
+            if (tau != 0.0) tangent_step(A.mu, A.mu1, tau, Sx, SP);
+            double da, db, ga[3], gb[3], dr = 0, gq[3] = {0, 0, 0};
+            if (!residual_and_grad(row, Sx, da, db, ga, gb, ranged, dr, gq)) {
+                da = db = dr = NAN;
+                ga[0] = ga[1] = ga[2] = gb[0] = gb[1] = gb[2] = gq[0] = gq[1] = gq[2] = NAN;
+            }
+            double ja[6], jb[6], jr[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                ja[c] = is * fma(ga[0], SP[c], fma(ga[1], SP[6 + c], ga[2] * SP[12 + c]));
+                jb[c] = is * fma(gb[0], SP[c], fma(gb[1], SP[6 + c], gb[2] * SP[12 + c]));
+                jr[c] = isr * fma(gq[0], SP[c], fma(gq[1], SP[6 + c], gq[2] * SP[12 + c]));
+            }
+            const double ra = da * is, rb = db * is, rr = dr * isr;
+            c2 = fma(ra, ra, fma(rb, rb, c2));
+            int t = 0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                gr[r] = fma(ja[r], ra, fma(jb[r], rb, gr[r]));
+#pragma unroll
+                for (int c = r; c < 6; ++c, ++t) N[t] = fma(ja[r], ja[c], fma(jb[r], jb[c], N[t]));
+            }
+            if (ranged) {
+                c2 = fma(rr, rr, c2);
+                t = 0;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    gr[r] = fma(jr[r], rr, gr[r]);
+#pragma unroll
+                    for (int c = r; c < 6; ++c, ++t) N[t] = fma(jr[r], jr[c], N[t]);
+                }
+            }
+            ++k;
+        }
+        if (n < S) tangent_step(A.mu, A.mu1, A.h, X, Phi);
+    }
+    if (valid) {
+        const int64_t o = D.off + i;
+        chi2[o] = c2;
+#pragma unroll
+        for (int d = 0; d < 21; ++d) jtj[d * B.ld + o] = N[d];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) jtr[d * B.ld + o] = gr[d];
+    }
+}
+
+// Damped Gauss-Newton step per candidate (column o of B's layout): solve
+// (N + lambda diag(N)) dx = -gscale g by Cholesky (gscale g = J^T r; the
+// adjoint gives g = grad chi2 = 2 J^T r) and write the trial state x + dx.
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_gn_solve(ProbDesc d0, SwarmArrays B,
+                                                 const double *__restrict__ jtj,
+                                                 const double *__restrict__ g, double gscale,
+                                                 const double *__restrict__ lam,
+                                                 double *__restrict__ xt)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t li = tile * BS + threadIdx.x;
+    if (li >= D.m) return;
+    const int64_t i = D.off + li, ld = B.ld;
+    const double *x = B.x;
+    double M[6][6], r[6];
+    int t = 0;
+    for (int a = 0; a < 6; ++a)
+        for (int b = a; b < 6; ++b, ++t) M[a][b] = M[b][a] = jtj[t * ld + i];
+    const double l = lam[i];
+    for (int a = 0; a < 6; ++a) {
+        M[a][a] = M[a][a] * (1.0 + l);
+        r[a] = -gscale * g[a * ld + i];
+    }
+    // Cholesky M = L L^T in place (lower triangle)
+    bool ok = true;
+    for (int a = 0; a < 6; ++a) {
+        double s = M[a][a];
+        for (int c = 0; c < a; ++c) s -= M[a][c] * M[a][c];
+        if (!(s > 0.0)) ok = false;
+        const double da = sqrt(s);
+        M[a][a] = da;
+        for (int b = a + 1; b < 6; ++b) {
+            double v = M[b][a];
+            for (int c = 0; c < a; ++c) v -= M[b][c] * M[a][c];
+            M[b][a] = v / da;
+        }
+    }
+    for (int a = 0; a < 6; ++a) {
+        double v = r[a];
+        for (int c = 0; c < a; ++c) v -= M[a][c] * r[c];
+        r[a] = v / M[a][a];
+    }
+    for (int a = 5; a >= 0; --a) {
+        double v = r[a];
+        for (int c = a + 1; c < 6; ++c) v -= M[c][a] * r[c];
+        r[a] = v / M[a][a];
+    }
+    for (int d = 0; d < 6; ++d) xt[d * ld + i] = x[d * ld + i] + (ok ? r[d] : 0.0);
+}
+
+// Candidate gather: column (p * stride + j) of dst gets the personal best of
+// particle cand[p][j] of problem p (or, past the selected candidates, a copy
+// of the first one so every column holds a valid state).
+__global__ __launch_bounds__(64) void k_gather(SwarmArrays B, const int32_t *__restrict__ cand,
+                                               int32_t top_k, double *__restrict__ dst,
+                                               int64_t dld, int64_t stride)
+{
+    const int64_t p = blockIdx.x;
+    const ProbDesc &D = B.desc[p];
+    for (int j = threadIdx.x; j < stride; j += blockDim.x) {
+        int32_t i = j < top_k ? cand[p * top_k + j] : -1;
+        if (i < 0) i = cand[p * top_k];
+        if (i < 0) i = 0;
+        for (int d = 0; d < 6; ++d) dst[d * dld + p * stride + j] = B.p[d * B.ld + D.off + i];
+    }
+}
+
+// Per problem: the candidate column with the lowest (chi2, column) among its
+// n[p] candidates at p * stride; writes its state (best [6][nprob]) and chi2.
+__global__ __launch_bounds__(64) void k_pick_best(const double *__restrict__ x,
+                                                  const double *__restrict__ chi2,
+                                                  const int32_t *__restrict__ n, int64_t ld,
+                                                  int64_t stride, double *__restrict__ best,
+                                                  double *__restrict__ best_chi2)
+{
+    const int64_t nprob = gridDim.x;
+    __shared__ double red[2];
+    const int64_t p = blockIdx.x;
+    double key = INFINITY, idx = INFINITY;
+    for (int j = threadIdx.x; j < n[p]; j += blockDim.x) {
+        const double k = cost_key(chi2[p * stride + j]);
+        if (lex_less(k, (double)j, key, idx)) {
+            key = k;
+            idx = (double)j;
+        }
+    }
+    block_argmin(key, idx, red);
+    if (threadIdx.x < 6) {
+        const int64_t j = idx < INFINITY ? (int64_t)idx : 0;
+        best[threadIdx.x * nprob + p] = x[threadIdx.x * ld + p * stride + j];
+    }
+    if (threadIdx.x == 0) best_chi2[p] = idx < INFINITY ? key : NAN;
+}
+
+// Accept the trial where its chi2 is strictly lower (and finite); adapt the
+// damping (/10 on success, *10 on failure). lam is initialised on the first
+// iteration (first != 0).
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_gn_accept(ProbDesc d0, SwarmArrays B,
+                                                  const double *__restrict__ xt,
+                                                  double *__restrict__ chi2,
+                                                  const double *__restrict__ chi2t,
+                                                  double *__restrict__ lam)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t li = tile * BS + threadIdx.x;
+    if (li >= D.m) return;
+    const int64_t i = D.off + li, ld = B.ld;
+    double *x = B.x;
+    const double c = chi2[i], ct = chi2t[i];
+    if (ct < c) {
+        for (int d = 0; d < 6; ++d) x[d * ld + i] = xt[d * ld + i];
+        chi2[i] = ct;
+        lam[i] = fmax(lam[i] * 0.1, 1e-12);
+    } else {
+        lam[i] = fmin(lam[i] * 10.0, 1e12);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+
+hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st)
+{
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_grad<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, grad, work, wld, mode);
+                        else hipLaunchKernelGGL((k_grad<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, grad, work, wld, mode));
+    return hipGetLastError();
+}
+
+hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                         double *chi2, double *jtj, double *jtr, hipStream_t st)
+{
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_normal<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr);
+                        else hipLaunchKernelGGL((k_normal<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr));
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                           const double *jtj, const double *g, double gscale, const double *lam,
+                           double *xt, hipStream_t st)
+{
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_gn_solve<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, jtj, g, gscale, lam, xt);
+                        else hipLaunchKernelGGL((k_gn_solve<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, jtj, g, gscale, lam, xt));
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k, double *dst,
+                         int64_t dld, int64_t stride, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)B.nprob), dim3(64), 0, st, B, cand, top_k, dst, dld, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_best(const double *x, const double *chi2, const int32_t *n, int64_t nprob,
+                            int64_t ld, int64_t stride, double *best, double *best_chi2,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pick_best, dim3((unsigned)nprob), dim3(64), 0, st, x, chi2, n, ld, stride, best, best_chi2);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_accept(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                            const double *xt, double *chi2, const double *chi2t, double *lam,
+                            hipStream_t st)
+{
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_gn_accept<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, xt, chi2, chi2t, lam);
+                        else hipLaunchKernelGGL((k_gn_accept<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, xt, chi2, chi2t, lam));
+    return hipGetLastError();
+}
+
+// lam[col] = value for the valid columns of the layout.
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_fill_cols(ProbDesc d0, SwarmArrays B, double *out,
+                                                  double value)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t li = tile * BS + threadIdx.x;
+    if (li < D.m) out[D.off + li] = value;
+}
+
+hipError_t launch_fill_cols(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
+                            double *out, double value, hipStream_t st)
+{
+    const bool single = B.desc == nullptr;
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_fill_cols<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, out, value);
+                        else hipLaunchKernelGGL((k_fill_cols<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, out, value));
+    return hipGetLastError();
+}
+
+}  // namespace iodk
