@@ -55,19 +55,20 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """Calibrated HBM bytes per launch of the iteration kernel from the
-    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE), or None if
-    the kernel source changed since the counters were taken."""
+def load_counters():
+    """From the committed rocprofv3 counter summary of the iteration kernel:
+    calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE) and FP64
+    operations per evaluating launch ((2 FMA + MUL + ADD) x 64); None for
+    both if the kernel sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
-        return None
+        return None, None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel_sha") != kernel_hash():
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+        return None, None
+    return float(kv["hbm_bytes_per_launch"]), float(kv["total_64_ops_per_eval_launch"])
 
 
 # The paper's variants beside Algorithm 1 (all off in the default run).
@@ -141,6 +142,31 @@ def cpu_baseline(wl, obs, target_s):
                       f"{el:.1f} s wall"}
 
 
+def gpu_screen(iod, torch, mu, h, arc_max):
+    """Close-approach screen of the uneven batch's draws (workloads.c2): the
+    chief and the true deputy of every draw are propagated by the library
+    (iod_propagate, one launch for all of them) to the screen's sample times
+    and checked against the Moon / Earth distances."""
+    from paper_2207_13175_amd import workloads as W
+    ts = W.screen_times(arc_max)
+    hd = iod.iod_create(mu, W.C0_CHIEF, ts, np.zeros((len(ts), 2)), 1.0, h=h)
+
+    def screen(chief, truth, arc):
+        n = len(chief)
+        xs = np.concatenate([chief, truth])
+        ld = (2 * n + 63) // 64 * 64
+        x = torch.zeros((6, ld), dtype=torch.float64, device="cuda")
+        x[:, :2 * n] = torch.from_numpy(np.ascontiguousarray(xs.T)).cuda()
+        st = torch.empty((len(ts), 6, ld), dtype=torch.float64, device="cuda")
+        iod.iod_propagate(hd, x, 2 * n, st)
+        pos = st[:, :3, :2 * n].permute(2, 0, 1).cpu().numpy().copy()   # [2n, S, 3]
+        arcs = np.concatenate([arc, arc])
+        pos[ts[None, :] > arcs[:, None] + 1e-12] = np.nan
+        bad = W.close_approach(mu, pos)
+        return bad[:n] | bad[n:]
+    return screen
+
+
 def batch_with_observations(iod, wl, ranges=False):
     """Batch whose observed angles (and, with ranges, ranges) are the
     library's prediction for each problem's true deputy plus seeded noise."""
@@ -165,7 +191,7 @@ def run_refine(args, iod, torch):
     problem's 16 best personal bests, against the plain FP64 swarm on the
     same 4,096 problems; problem solves/s and final position errors."""
     from paper_2207_13175_amd import workloads as W
-    wl = W.c4(0)
+    wl = W.c4(0, screen=gpu_screen(iod, torch, W.MU_EARTH_MOON, 1e-3, 2.6))
     if args.iters is not None:
         wl.n_iter = args.iters
     b = batch_with_observations(iod, wl)
@@ -217,7 +243,7 @@ def run_batch(args, iod, torch, top_k=0):
     personal bests per problem per iteration), compared with an untimed FP64
     solve of the same batch."""
     from paper_2207_13175_amd import workloads as W
-    wl = W.c2(0)
+    wl = W.c2(0, screen=gpu_screen(iod, torch, W.MU_EARTH_MOON, 1e-3, 3.1))
     if args.iters is not None:
         wl.n_iter = args.iters
     b = batch_with_observations(iod, wl, ranges=args.variant == "range")
@@ -398,6 +424,8 @@ def main():
     n_run = int(np.max(np.flatnonzero(~np.isnan(hist))))
     launch_ms = [e0.elapsed_time(e1) for row in evs for (e0, e1) in row[:n_run]]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    # evaluating launches only (iteration 1 reuses the initial evaluation)
+    med_eval_ms = float(np.median([e0.elapsed_time(e1) for row in evs for (e0, e1) in row[1:n_run]]))
     # average algorithmic work of one iteration-kernel launch: every launch
     # updates m particles, all but the first iteration also evaluate them
     flop_eval = steps_per_eval * FLOP_PER_STEP + wl.K * FLOP_PER_OBS
@@ -408,6 +436,8 @@ def main():
     ps_per_solve = n_run * wl.m * steps_per_eval
     value = args.steps * ps_per_solve / elapsed
 
+    traffic, ops64 = load_counters() if (args.workload == "c1" and args.variant == "none") else (None, None)
+    counter_tflops = (ops64 * (n_run - 1) / n_run / avg_launch_s / 1e12) if ops64 else None
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -424,9 +454,15 @@ def main():
                        float(np.linalg.norm(best[0][:3] - wl.truth[:3]))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": load_traffic() if args.workload == "c1" else None,
-                     "kernel": "k_swarm_iter", "avg_launch_ms": avg_launch_s * 1e3,
-                     "flop_per_launch": flop_launch},
+                     "traffic": traffic, "kernel": "k_swarm_iter",
+                     "avg_launch_ms": avg_launch_s * 1e3,
+                     "median_eval_launch_ms": med_eval_ms,
+                     "flop_per_launch": flop_launch,
+                     # second reading: FP64 operations counted by the hardware
+                     # (profiles/k_swarm_iter_c1_fp64.md) over the same launches
+                     "counter_achieved": counter_tflops,
+                     "counter_frac": (counter_tflops / PEAK_FP64_TFLOPS
+                                      if counter_tflops is not None else None)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, obs, args.cpu_seconds)

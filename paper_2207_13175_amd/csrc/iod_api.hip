@@ -382,6 +382,7 @@ void single_view(const iod_handle *h, const iod_swarm *s, const iod_pso_params *
     B.slots = s->work;
     B.recs = s->work + 2 * nslots * REC;
     B.stop = B.recs + 2 * REC;
+    B.porder = nullptr;
     set_grid(D, p, s->m);
     B.ld = s->ld;
     B.total_slots = nslots;
@@ -822,6 +823,7 @@ namespace {
 // Device-side layout of one batched launch: descriptors and work list.
 struct BatchLayout {
     std::vector<ProbDesc> descs;
+    std::vector<int32_t> porder;  // [P] problem order of the work list
     std::vector<int32_t> work;  // [grid][2]
     int64_t ld = 0, total_slots = 0, grid = 0;
 };
@@ -853,6 +855,7 @@ int batch_layout(const iod_batch *b, const iod_pso_params *params, const int64_t
         std::stable_sort(pord.begin(), pord.end(), [&](int32_t a, int32_t c) {
             return b->probs[a].steps > b->probs[c].steps;
         });
+    L.porder = pord;
     L.work.clear();
     for (int32_t p : pord)
         for (int64_t t = 0; t < L.descs[p].nslots; ++t) {
@@ -888,10 +891,12 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     const int64_t P = b->P, ld = L.ld;
     const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1) + P);
     Stream st;
-    DevBuf dbuf, ddesc, dwork, dcand;
+    DevBuf dbuf, ddesc, dwork, dcand, dpord;
     HIP_TRY(hipStreamCreate(&st.s));
     HIP_TRY(hipMalloc(&dbuf.p, nd * sizeof(double)));
     if (top_k > 0) HIP_TRY(hipMalloc(&dcand.p, (size_t)P * top_k * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&dpord.p, (size_t)P * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(dpord.p, L.porder.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice, st.s));
     int32_t *cand = (int32_t *)dcand.p;
     double *base = (double *)dbuf.p;
     double *hist = base + 20 * ld + 2 * L.total_slots * REC + 2 * P * REC;
@@ -915,6 +920,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     B.slots = base + 20 * ld;
     B.recs = B.slots + 2 * L.total_slots * REC;
     B.stop = stop;
+    B.porder = (const int32_t *)dpord.p;
     B.ld = ld;
     B.total_slots = L.total_slots;
     B.nprob = P;

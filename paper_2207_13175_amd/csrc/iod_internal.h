@@ -70,6 +70,8 @@ struct SwarmArrays {
     double *slots;              // [2][total_slots][REC]
     double *recs;               // [2][nprob][REC]
     double *stop;               // [nprob] Algorithm 2: -1 running, else the last iteration run
+    const int32_t *porder;      // [nprob] problems by RK4 steps, longest first (per-problem
+                                // launches dispatch in this order), or null: index order
     int64_t ld, total_slots, nprob;
 };
 

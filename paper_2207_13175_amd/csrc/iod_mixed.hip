@@ -324,7 +324,7 @@ __global__ __launch_bounds__(TOPK_BS) void k_topk(SwarmArrays B, const double *_
                                                   int32_t top_k, int32_t *__restrict__ out)
 {
     __shared__ double sk[2 * TOPK_BS], si[2 * TOPK_BS];
-    const int64_t p = blockIdx.x;
+    const int64_t p = B.porder ? B.porder[blockIdx.x] : blockIdx.x;
     const ProbDesc &D = B.desc[p];
     const int t = threadIdx.x;
     // running best list in [0, TOPK_BS), new chunk in [TOPK_BS, 2 TOPK_BS)
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *_
     __shared__ int32_t lds_ns[OBS_CHUNK];
     __shared__ double red[2];
     __shared__ double wst[6];
-    const int64_t p = blockIdx.x;
+    const int64_t p = B.porder ? B.porder[blockIdx.x] : blockIdx.x;
     const ProbDesc &D = B.desc[p];
     const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
     double *cur = B.recs + ((n & 1) * B.nprob + p) * REC;

@@ -157,42 +157,95 @@ class BatchWorkload:
         return int(self.n_iter) * int(np.sum(self.m * self.steps()))
 
 
+# Close-approach screen of the uneven batch: a draw whose chief or true
+# deputy passes within these distances of the Moon / the Earth over its arc
+# is redrawn.
+MOON_MIN_LU = 0.02
+EARTH_MIN_LU = 0.1
+SCREEN_DT = 0.005   # sampling interval of the screen (TU)
+
+
+def screen_times(arc_max: float) -> np.ndarray:
+    """Sample times of the close-approach screen, every SCREEN_DT TU up to arc_max."""
+    return np.arange(1, int(np.floor(arc_max / SCREEN_DT + 1e-9)) + 1) * SCREEN_DT
+
+
+def close_approach(mu: float, positions: np.ndarray) -> np.ndarray:
+    """positions [n, S, 3] sampled along n trajectories (NaN-padded past each
+    arc) -> bool [n]: some sample lies within MOON_MIN_LU of the Moon at
+    (1 - mu, 0, 0) or within EARTH_MIN_LU of the Earth at (-mu, 0, 0), or is
+    not finite."""
+    moon = np.linalg.norm(positions - np.array([1.0 - mu, 0.0, 0.0]), axis=2)
+    earth = np.linalg.norm(positions - np.array([-mu, 0.0, 0.0]), axis=2)
+    bad = np.nanmin(np.where(np.isnan(moon), np.inf, moon), axis=1) < MOON_MIN_LU
+    bad |= np.nanmin(np.where(np.isnan(earth), np.inf, earth), axis=1) < EARTH_MIN_LU
+    return bad
+
+
+def _draw_problem(rng, h, K_range, T_range, m_range, sigma):
+    base = L1_X if rng.random() < 0.5 else L2_X
+    chief = np.zeros(6)
+    chief[0] = base + rng.uniform(-0.02, 0.02)
+    chief[2] = rng.uniform(-0.1, 0.1)
+    chief[3:] = uniform_ball(rng, 0.3)
+    truth = chief.copy()
+    truth[:3] += uniform_ball(rng, 1e-3)
+    truth[3:] += rng.uniform(-1e-3, 1e-3, 3)
+    K = int(rng.integers(K_range[0], K_range[1] + 1))
+    T = rng.uniform(*T_range)
+    per = max(1, int(round(T / (K * h))))   # whole steps between observations
+    t = np.arange(1, K + 1, dtype=np.float64) * (per * h)
+    noise = rng.standard_normal((K, 2)) * sigma
+    m = int(round(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+    return chief, truth, t, noise, m
+
+
 def c2(seed: int = 0, P: int = 1024, n_iter: int = 150, m_range=(512, 8192),
-       K_range=(5, 80), T_range=(0.2, 3.0), h: float = 1e-3, sigma: float = 1e-5) -> BatchWorkload:
+       K_range=(5, 80), T_range=(0.2, 3.0), h: float = 1e-3, sigma: float = 1e-5,
+       screen=None) -> BatchWorkload:
     """Batched uneven problems: chief x = L1 or L2 + U(+-0.02), y = 0,
     z ~ U(+-0.1), velocity uniform in a ball of radius 0.3; K ~ U{5..80};
     arc T ~ U(0.2, 3.0) snapped to a multiple of K h; m log-uniform in
     [512, 8192]; deputy offsets, box and sigma as the small case; h = 1e-3,
-    150 iterations."""
-    rng = np.random.default_rng([seed, 4])
-    chief = np.zeros((P, 6))
-    truth = np.zeros((P, 6))
-    ts, noise = [], []
-    m = np.zeros(P, dtype=np.int64)
-    for p in range(P):
-        base = L1_X if rng.random() < 0.5 else L2_X
-        chief[p, 0] = base + rng.uniform(-0.02, 0.02)
-        chief[p, 2] = rng.uniform(-0.1, 0.1)
-        chief[p, 3:] = uniform_ball(rng, 0.3)
-        truth[p] = chief[p]
-        truth[p, :3] += uniform_ball(rng, 1e-3)
-        truth[p, 3:] += rng.uniform(-1e-3, 1e-3, 3)
-        K = int(rng.integers(K_range[0], K_range[1] + 1))
-        T = rng.uniform(*T_range)
-        per = max(1, int(round(T / (K * h))))   # whole steps between observations
-        ts.append(np.arange(1, K + 1, dtype=np.float64) * (per * h))
-        noise.append(rng.standard_normal((K, 2)) * sigma)
-        m[p] = int(round(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+    150 iterations. Problem p draws from its own stream (seed, 4, p).
+
+    screen(chief [n, 6], truth [n, 6], arc [n]) -> bool [n], if given, marks
+    draws to redraw (from the same problem's stream, until none is marked):
+    the close-approach screen, which needs the dynamics and is therefore
+    supplied by the caller (see close_approach and screen_times)."""
+    rngs = [np.random.default_rng([seed, 4, p]) for p in range(P)]
+    draws = [_draw_problem(rngs[p], h, K_range, T_range, m_range, sigma) for p in range(P)]
+    if screen is not None:
+        todo = np.arange(P)
+        for _ in range(1000):
+            ch = np.array([draws[p][0] for p in todo])
+            tr = np.array([draws[p][1] for p in todo])
+            arc = np.array([draws[p][2][-1] for p in todo])
+            bad = np.asarray(screen(ch, tr, arc), dtype=bool)
+            todo = todo[bad]
+            if len(todo) == 0:
+                break
+            for p in todo:
+                draws[p] = _draw_problem(rngs[p], h, K_range, T_range, m_range, sigma)
+        else:
+            raise RuntimeError("close-approach screen did not settle")
+    chief = np.array([d[0] for d in draws])
+    truth = np.array([d[1] for d in draws])
+    ts = [d[2] for d in draws]
+    noise = [d[3] for d in draws]
+    m = np.array([d[4] for d in draws], dtype=np.int64)
     return BatchWorkload(f"c2_P{P}_N{n_iter}", MU_EARTH_MOON, h, sigma, chief, truth, ts, noise,
                          m, n_iter, chief - 2e-3, chief + 2e-3, pso_seed=seed)
 
 
-def c4(seed: int = 0, P: int = 4096, n_iter: int = 100, m: int = 2048) -> BatchWorkload:
-    """Refinement workload: 4,096 problems drawn as the uneven batch but with
-    K ~ U{10..60}, arcs T ~ U(0.5, 2.5) and 2,048 particles each, 100
-    iterations; each problem's best personal bests are then refined."""
+def c4(seed: int = 0, P: int = 4096, n_iter: int = 100, m: int = 2048,
+       screen=None) -> BatchWorkload:
+    """Refinement workload: 4,096 problems drawn as the uneven batch (same
+    close-approach screen) but with K ~ U{10..60}, arcs T ~ U(0.5, 2.5) and
+    2,048 particles each, 100 iterations; each problem's best personal bests
+    are then refined."""
     wl = c2(seed + 1000, P=P, n_iter=n_iter, m_range=(m, m), K_range=(10, 60),
-            T_range=(0.5, 2.5))
+            T_range=(0.5, 2.5), screen=screen)
     wl.name = f"c4_P{P}_m{m}_N{n_iter}"
     wl.m = np.full(P, m, dtype=np.int64)
     return wl

@@ -337,3 +337,26 @@ def test_eval_parity_mass_parameter_range(torch_dev, mu):
     got = st.cpu().numpy()
     for i in (0, 5, 6, 77):
         assert np.array_equal(got[:, :, i], oracle.propagate(mu, wl.h, xs[i], wl.t)), i
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_brute_force_slice_grid(torch_dev, noise):
+    """A 201 x 201 grid over (x0, vy0) of a tiny problem (3 observations over
+    0.1 TU), the true state on the centre node: every grid cost matches the
+    oracle, the two arg-mins coincide, and without noise the minimum sits on
+    the truth."""
+    torch, dev = torch_dev
+    wl = W.tiny(0, K=3, T=0.1)
+    P, obs = make_problem(wl, noise=noise)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    off = np.linspace(-1e-3, 1e-3, 201)
+    dx, dv = np.meshgrid(off, off, indexing="ij")
+    xs = np.repeat(wl.truth[None, :], dx.size, axis=0)
+    xs[:, 0] += dx.ravel()
+    xs[:, 4] += dv.ravel()
+    got = gpu_cost(torch, dev, h, xs)
+    want = oracle.cost(P, xs)
+    assert_cost_parity(got, want)
+    assert np.argmin(got) == np.argmin(want)
+    if not noise:
+        assert np.argmin(got) == 100 * 201 + 100

@@ -337,7 +337,14 @@ def test_algorithm2_batch_equals_single(torch_dev):
         obs.append(oracle.predict(P0, wl.truth[p]) + wl.noise[p])
         probs.append(P0.with_angles(obs[-1]))
     b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
-    tau = 1e-3
+    # a tolerance that part of the untruncated histories cross
+    Ks = []
+    for p in range(wl.P):
+        S0 = oracle.Pso(0.7, 1.5, 1.5, 2, wl.lo[p], wl.hi[p], problem=p)
+        _, _, hf, _ = oracle.pso_solve(probs[p], S0, int(wl.m[p]), wl.n_iter)
+        Ks += [0.0 if hf[n] == hf[n - 5] else abs((hf[n] - hf[n - 5]) / hf[n])
+               for n in range(6, wl.n_iter + 1)]
+    tau = float(np.quantile(Ks, 0.3))
     params = [iod.pso_params(0.7, 1.5, 1.5, 2, wl.lo[p], wl.hi[p], problem=p, tol=tau, tol_lag=5)
               for p in range(wl.P)]
     g, J, hist = iod.iod_batch_solve(b, params, wl.m, wl.n_iter)
@@ -362,10 +369,15 @@ def test_algorithm2_mixed_precision(torch_dev):
         P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief[p], wl.t[p], np.zeros((len(wl.t[p]), 2)))
         obs.append(oracle.predict(P0, wl.truth[p]) + wl.noise[p])
     b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
-    lag, tau = 5, 1e-3
+    lag = 5
+    free = [iod.pso_params(0.7, 1.5, 1.5, 2, wl.lo[p], wl.hi[p], problem=p) for p in range(wl.P)]
+    _, _, hf = iod.iod_batch_solve_mixed(b, free, wl.m, wl.n_iter, top_k=32)
+    tau = float(np.quantile([0.0 if hp[n] == hp[n - lag] else abs((hp[n] - hp[n - lag]) / hp[n])
+                             for hp in hf for n in range(lag + 1, wl.n_iter + 1)], 0.3))
     params = [iod.pso_params(0.7, 1.5, 1.5, 2, wl.lo[p], wl.hi[p], problem=p, tol=tau, tol_lag=lag)
               for p in range(wl.P)]
     g, J, hist = iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=32)
+    assert np.any(np.isnan(hist))                             # some problem stopped early
     for p in range(wl.P):
         hp = hist[p]
         fin = np.flatnonzero(~np.isnan(hp))
@@ -377,3 +389,5 @@ def test_algorithm2_mixed_precision(torch_dev):
             assert met == [last], (p, met, last)              # stopped at the first crossing
         else:
             assert met in ([], [last]), (p, met)
+        # up to its stop the run is the untruncated one
+        assert np.array_equal(hp[:last + 1], hf[p][:last + 1]), p
