@@ -98,7 +98,10 @@ typedef struct {
  * with r1 the distance to the larger primary at (-mu,0,0) and r2 to the
  * smaller at (1-mu,0,0). (The paper's y equation writes "mu" without the
  * backslash in r1; it is the same mu.) The common factor (1-mu)/r1^3 + mu/r2^3
- * of the y and z terms is formed once. */
+ * of the y and z terms is formed once. Both inverse cubes come from one
+ * reciprocal: with D_j = r_j^2 sqrt(r_j^2) = r_j^3 and R = 1/(D1 D2),
+ * (1-mu)/r1^3 = (1-mu)(D2 R) and mu/r2^3 = mu (D1 R) (the paper gives the
+ * accelerations, not an evaluation order). */
 void orc_rhs(double mu, const double s[6], double f[6])
 {
     const double mu1 = 1.0 - mu;
@@ -109,8 +112,11 @@ void orc_rhs(double mu, const double s[6], double f[6])
     const double q = fma(z, z, y * y);   /* y^2 + z^2 */
     const double r1s = fma(d1, d1, q);   /* r1^2 */
     const double r2s = fma(d2, d2, q);   /* r2^2 */
-    const double c1 = mu1 / (r1s * sqrt(r1s));  /* (1-mu)/r1^3 */
-    const double c2 = mu / (r2s * sqrt(r2s));   /* mu/r2^3 */
+    const double D1 = r1s * sqrt(r1s);   /* r1^3 */
+    const double D2 = r2s * sqrt(r2s);   /* r2^3 */
+    const double R = 1.0 / (D1 * D2);    /* 1/(r1^3 r2^3) */
+    const double c1 = mu1 * (D2 * R);    /* (1-mu)/r1^3 */
+    const double c2 = mu * (D1 * R);     /* mu/r2^3 */
     const double cs = c1 + c2;
     f[0] = s[3];
     f[1] = s[4];

@@ -56,17 +56,19 @@ __device__ __forceinline__ double div_inrange(double a, double b)
 //   ax =  2 vy + x - (1-mu)(x+mu)/r1^3 - mu (x-(1-mu))/r2^3
 //   ay = -2 vx + y - ((1-mu)/r1^3 + mu/r2^3) y
 //   az =           - ((1-mu)/r1^3 + mu/r2^3) z
-// with c_j = mu_j / (r_j^2 sqrt(r_j^2)), sqrt and division correctly rounded.
+// with both inverse cubes from one reciprocal: D_j = r_j^2 sqrt(r_j^2),
+// R = 1/(D1 D2), c1 = (1-mu)(D2 R), c2 = mu (D1 R); sqrt and the reciprocal
+// correctly rounded.
 //
 // INRANGE = true uses the in-range sequences and returns whether the result
-// is certified equal to the IEEE one: c1 + c2 <= 2^600 and c1 >= 2^-700
-// (with mu = 0 or mu >= 2^-60). Any input outside the sequences' domain
-// (r_j^2 zero, denormal, below 2^-767, infinite or NaN; r_j^3 overflowing
-// or denormal) drives c_j to NaN, 0 or above 2^600, so it fails the test;
-// a passing c1 bounds r1^3 within [2^-601, 2^700], hence r2^3 <= ~2^701, so
-// both divisions have normal operands, normal quotients and exponent gaps
-// below 768, and both radicands lie in [2^-767, 2^468]. INRANGE = false is
-// the IEEE path (always certified).
+// is certified equal to the IEEE one: 2^-760 <= D1 D2 <= 2^1000. The
+// reciprocal then has a normal operand, a normal result and an exponent gap
+// below 768. Both radicands are in range as well: r_j^2 < 2^-767 would need
+// the other primary's D above 2^390, but the primaries are one unit apart,
+// so r_j ~ 0 puts the other at r ~ 1; an infinite or NaN radicand makes
+// D1 D2 infinite or NaN. mu enters only through products, so every mu in
+// [0, 0.5] takes the in-range path. INRANGE = false is the IEEE path (always
+// certified).
 template <bool INRANGE>
 __device__ __forceinline__ bool rhs(double mu, double mu1, const double s[6], double f[6])
 {
@@ -76,14 +78,12 @@ __device__ __forceinline__ bool rhs(double mu, double mu1, const double s[6], do
     const double q = fma(z, z, y * y);
     const double r1s = fma(d1, d1, q);
     const double r2s = fma(d2, d2, q);
-    double c1, c2;
-    if (INRANGE) {
-        c1 = div_inrange(mu1, r1s * sqrt_inrange(r1s));
-        c2 = div_inrange(mu, r2s * sqrt_inrange(r2s));
-    } else {
-        c1 = mu1 / (r1s * sqrt(r1s));
-        c2 = mu / (r2s * sqrt(r2s));
-    }
+    const double D1 = r1s * (INRANGE ? sqrt_inrange(r1s) : sqrt(r1s));
+    const double D2 = r2s * (INRANGE ? sqrt_inrange(r2s) : sqrt(r2s));
+    const double D = D1 * D2;
+    const double R = INRANGE ? div_inrange(1.0, D) : 1.0 / D;
+    const double c1 = mu1 * (D2 * R);
+    const double c2 = mu * (D1 * R);
     const double cs = c1 + c2;
     f[0] = s[3];
     f[1] = s[4];
@@ -91,7 +91,7 @@ __device__ __forceinline__ bool rhs(double mu, double mu1, const double s[6], do
     f[3] = fma(-c2, d2, fma(-c1, d1, fma(2.0, vy, x)));
     f[4] = fma(-cs, y, fma(-2.0, vx, y));
     f[5] = -(cs * z);
-    return !INRANGE || (cs <= 0x1p600 && c1 >= 0x1p-700);
+    return !INRANGE || (D >= 0x1p-760 && D <= 0x1p1000);
 }
 
 // Classical RK4 step of size h (h2 = h/2, h6 = h/6) from X into Y. The stage

@@ -29,7 +29,7 @@ struct KArgs {
     const int32_t *ns;  // device [K] whole steps before each observation
     int32_t K;
     int32_t mode;       // 0 = sum e_k^2, 1 = sum e_k
-    bool fast;          // mu == 0 or mu >= 2^-60: in-range sqrt/div allowed
+    bool fast;          // in-range sqrt/reciprocal sequences allowed (false: IEEE path only)
     double mu, mu1;     // mu and 1 - mu
     double h, h2, h6;   // h, h/2, h/6
     double w;           // 1 / sigma^2
