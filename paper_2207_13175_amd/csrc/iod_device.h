@@ -130,19 +130,38 @@ __device__ __forceinline__ bool rk4_into(double mu, double mu1, double h, double
     return ok;
 }
 
-// One RK4 step in place. The step runs with the in-range sequences; if any
-// lane of the wave is not certified, the wave repeats the step from X on the
-// IEEE path. Both give the same bits wherever the first is certified, so
+// One RK4 step from X into Y. The step runs with the in-range sequences; if
+// any lane of the wave is not certified, the wave repeats the step from X on
+// the IEEE path. Both give the same bits wherever the first is certified, so
 // the result is always that of correctly rounded sqrt and division.
+__device__ __forceinline__ void rk4_step(double mu, double mu1, bool fast, double h, double h2,
+                                         double h6, const double X[6], double Y[6])
+{
+    bool ok = false;
+    if (fast) ok = rk4_into<true>(mu, mu1, h, h2, h6, X, Y);
+    if (!__all(ok)) rk4_into<false>(mu, mu1, h, h2, h6, X, Y);
+}
+
+// One RK4 step in place.
 __device__ __forceinline__ void rk4(double mu, double mu1, bool fast, double h, double h2,
                                     double h6, double X[6])
 {
     double Y[6];
-    bool ok = false;
-    if (fast) ok = rk4_into<true>(mu, mu1, h, h2, h6, X, Y);
-    if (!__all(ok)) rk4_into<false>(mu, mu1, h, h2, h6, X, Y);
+    rk4_step(mu, mu1, fast, h, h2, h6, X, Y);
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = Y[d];
+}
+
+// n steps of size h in place, two at a time between two register sets so
+// that no copy is needed between steps.
+__device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6])
+{
+    double Y[6];
+    for (; n >= 2; n -= 2) {
+        rk4_step(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X, Y);
+        rk4_step(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y, X);
+    }
+    if (n == 1) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
 }
 
 // Walk the observation schedule: advance X on the grid, and at each
@@ -164,7 +183,10 @@ __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, i
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
             const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
-            for (; step < target; ++step) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
+            if (target > step) {
+                rk4_steps(A, target - step, X);
+                step = target;
+            }
             const double tau = row[TAB_TAU];
             double S[6];
 #pragma unroll
