@@ -199,20 +199,33 @@ def run_refine(args, iod, torch):
               for p in range(wl.P)]
     cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
     steps = iod.iod_batch_steps(b)
+    n_gn = args.gn_iters
     for _ in range(args.warmup):
-        iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16, n_gn=10)
+        iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16, n_gn=n_gn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g, chi2, J = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
-                                                  n_gn=10)
+                                                  n_gn=n_gn)
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / args.steps
     iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=0)
-    t1 = time.perf_counter()
-    g64, J64, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - t1
+    # plain FP64 swarm on the same problems at 1x, 2x and 4x the iterations:
+    # how long it needs to reach the refined error
+    curve = []
+    for mult in (1, 2, 4):
+        t1 = time.perf_counter()
+        gc, _, _ = iod.iod_batch_solve(b, params, wl.m, mult * wl.n_iter, history=False)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t1
+        ec = np.linalg.norm(gc[:, :3] - wl.truth[:, :3], axis=1)
+        curve.append((mult * wl.n_iter, tc, ec))
+        if mult == 1:
+            g64, t64 = gc, tc
+    # the precision gate: the same refinement after an FP64 swarm (untimed)
+    gp64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
+                                                  n_gn=n_gn)
+    dpol = np.max(np.abs(g - gp64), axis=1)
     err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
     e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
     q = lambda a: [float(np.quantile(a, v)) for v in (0.1, 0.5, 0.9)]
@@ -222,7 +235,7 @@ def run_refine(args, iod, torch):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl.name + "_mixed_top64_refine16x10", "problems": wl.P,
+        "config": {"workload": wl.name + f"_mixed_top64_refine16x{n_gn}", "problems": wl.P,
                    "particles": int(wl.m.sum()), "iterations": wl.n_iter,
                    "steps_range": [int(steps.min()), int(steps.max())],
                    "particle_steps_per_solve": ps,
@@ -232,7 +245,21 @@ def run_refine(args, iod, torch):
                    "fp64_swarm": {"problem_solves_per_s": wl.P / t64,
                                   "pos_err_q10_50_90": q(e64)},
                    "problems_at_least_as_accurate_as_fp64_swarm": int(np.sum(err <= e64)),
-                   "speedup_vs_fp64_swarm": t64 / elapsed},
+                   "speedup_vs_fp64_swarm": t64 / elapsed,
+                   # mixed swarm + refinement against FP64 swarm + the same refinement
+                   "refined_state_diff_vs_fp64_q50_90_max": [float(np.quantile(dpol, 0.5)),
+                                                             float(np.quantile(dpol, 0.9)),
+                                                             float(np.max(dpol))],
+                   "refined_within_1e-9_of_fp64": int(np.sum(dpol <= 1e-9)),
+                   "fp64_swarm_curve": [{"iterations": n, "problem_solves_per_s": wl.P / tc,
+                                         "pos_err_q10_50_90": q(ec)} for n, tc, ec in curve],
+                   # the first FP64 run whose median error is no worse than the refined one
+                   "speedup_at_equal_median_error": next(
+                       (tc / elapsed for n, tc, ec in curve if np.median(ec) <= np.median(err)),
+                       None),
+                   # where they differ: chi2 of the mixed result over that of the FP64 one
+                   "refined_chi2_ratio_where_different_q10_50_90":
+                       q(chi2[dpol > 1e-9] / chi64[dpol > 1e-9]) if np.any(dpol > 1e-9) else None},
     }
 
 
@@ -340,6 +367,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
+    ap.add_argument("--gn-iters", type=int, default=10,
+                    help="Gauss-Newton iterations of the refinement workload")
     ap.add_argument("--variant", default="none", choices=VARIANTS,
                     help="one of the paper's variants beside Algorithm 1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -72,6 +72,7 @@ def _create_raw(mu=0.0121, chief=None, t=None, ang=None, K=None, sigma=1e-5, opt
     dict(chief=[1, 0, np.inf, 0, 0, 0]),
     dict(sigma=0.0), dict(sigma=-1.0), dict(sigma=float("inf")),
     dict(K=0), dict(K=-3),
+    dict(t=np.arange(1, 65538) * 1e-6, ang=np.zeros((65537, 2))),   # K > IOD_MAX_OBS
     dict(t=[0.1, 0.05]), dict(t=[-0.1, 0.2]),
     dict(ang=[[0.0, np.nan]] * 10),
     dict(opt=iod.iod_options(0.0, 0, 0)), dict(opt=iod.iod_options(1e-3, 7, 0)),

@@ -360,3 +360,28 @@ def test_brute_force_slice_grid(torch_dev, noise):
     assert np.argmin(got) == np.argmin(want)
     if not noise:
         assert np.argmin(got) == 100 * 201 + 100
+
+
+def test_maximum_observation_count(torch_dev):
+    """K = IOD_MAX_OBS observations, one after every RK4 step (the table
+    streams through LDS in 1,024 chunks): states bitwise, costs within the
+    bar, on a ragged swarm."""
+    torch, dev = torch_dev
+    K = iod.IOD_MAX_OBS
+    h = 2e-5
+    t = np.arange(1, K + 1) * h
+    wl = W.tiny(5, K=3, T=0.1, h=h)
+    P0 = oracle.Problem(wl.mu, h, wl.sigma, wl.chief, t, np.zeros((K, 2)))
+    rng = np.random.default_rng(8)
+    obs = oracle.predict(P0, wl.truth) + rng.standard_normal((K, 2)) * wl.sigma
+    P = P0.with_angles(obs)
+    hd = iod.iod_create(wl.mu, wl.chief, t, obs, wl.sigma, h=h)
+    xs = W.random_swarm(7, 70, wl.lo, wl.hi)
+    assert_cost_parity(gpu_cost(torch, dev, hd, xs), oracle.cost(P, xs))
+    x = to_dev(torch, dev, xs[:3])
+    st = torch.zeros((K, 6, 64), dtype=torch.float64, device=dev)
+    iod.iod_propagate(hd, x, 3, st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    for i in range(3):
+        assert np.array_equal(got[:, :, i], oracle.propagate(wl.mu, h, xs[i], t)), i
