@@ -255,6 +255,14 @@ struct Stream {
     }
 };
 
+struct Event {
+    hipEvent_t e = nullptr;
+    ~Event()
+    {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 // Runs the iteration launches n0 + 1 .. n0 + n_iter, directly or as one
 // captured graph.
 template <class F>
@@ -940,26 +948,24 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
         HIP_TRY(launch_topk(B, B.jp, top_k, cand, st.s));
         HIP_TRY(launch_reeval64(B, cand, top_k, 0, st.s));
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Event e0, e1;
     if (iter_ms) {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventCreate(&e0.e));
+        HIP_TRY(hipEventCreate(&e1.e));
         // the first iteration reuses the initial evaluation: run it untimed
         HIP_TRY(iterate(1));
-        HIP_TRY(hipEventRecord(e0, st.s));
+        HIP_TRY(hipEventRecord(e0.e, st.s));
     }
     const int64_t n0 = iter_ms ? 1 : 0;
     rc = run_iterations(st.s, cfg.graph != 0, n0, n_iter - n0, iterate);
     if (rc == IOD_OK && iter_ms) {
-        hipError_t e = hipEventRecord(e1, st.s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        hipError_t e = hipEventRecord(e1.e, st.s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1.e);
         float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0.e, e1.e);
         if (e != hipSuccess) rc = hip_fail(e, "iteration timing");
         *iter_ms = n_iter > n0 ? ms / (double)(n_iter - n0) : 0.0;
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     if (rc == IOD_OK && top_k == 0) {
         hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
         if (e != hipSuccess) rc = hip_fail(e, "final launch");

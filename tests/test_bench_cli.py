@@ -1,0 +1,26 @@
+"""Host checks of the benchmark's command line (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_record_is_tied_to_the_kernel_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    traffic, ops = bench.load_counters()
+    # the committed record either matches the current sources or is ignored
+    with open(bench.TRAFFIC_FILE) as f:
+        sha = [l.split(":", 1)[1].strip() for l in f if l.startswith("kernel_sha")][0]
+    if sha == bench.kernel_hash():
+        assert traffic > 0 and ops > 0
+    else:
+        assert traffic is None and ops is None
