@@ -363,8 +363,8 @@ def run_batch(args, iod, torch, top_k=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
     ap.add_argument("--gn-iters", type=int, default=10,
@@ -442,8 +442,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     best = None
+    solve_ms = []
     for k in range(args.steps):
-        best = solve(evs[k])
+        ts = time.perf_counter()
+        best = solve(evs[k])          # ends with a synchronising read-back
+        solve_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -479,6 +482,7 @@ def main():
                    "rk4_steps_per_eval": steps_per_eval,
                    "particle_steps_per_solve": ps_per_solve,
                    "solves_per_s": args.steps / elapsed,
+                   "median_solve_ms": float(np.median(solve_ms)),
                    "gbest_cost": best[1], "gbest_pos_err_lu":
                        float(np.linalg.norm(best[0][:3] - wl.truth[:3]))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
