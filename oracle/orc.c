@@ -388,7 +388,7 @@ static double obs_error(const tables *T, int32_t k, const double rho[3])
 
 /* Cost J of one particle, eqs. (b:total) and (total:cost): per observation
  * e_k = b_k^T W b_k (obs_error); b_total = [e_1 ... e_K] is a row
- * vector and "the square of the row vector" is read as its inner product,
+ * vector whose square (the paper's wording) is read as its inner product,
  * J = sum_k e_k^2 (PAPER mode). CHI2 mode is J = sum_k e_k. Accumulated in
  * ascending k from +0. A zero line of sight makes e_k = +inf. */
 static double cost_one(const orc_problem *P, const tables *T, const double x0[6])
