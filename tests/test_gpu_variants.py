@@ -391,3 +391,54 @@ def test_algorithm2_mixed_precision(torch_dev):
             assert met in ([], [last]), (p, met)
         # up to its stop the run is the untruncated one
         assert np.array_equal(hp[:last + 1], hf[p][:last + 1]), p
+
+
+def ranged_batch(seed=7, P=6):
+    wl = W.c2(seed, P=P, n_iter=30, m_range=(128, 300), K_range=(6, 14), T_range=(0.3, 0.6))
+    probs, obs, ranges = [], [], []
+    for p in range(wl.P):
+        P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief[p], wl.t[p], np.zeros((len(wl.t[p]), 2)))
+        a = oracle.predict(P0, wl.truth[p]) + wl.noise[p]
+        r = oracle.predict_ranges(P0, wl.truth[p]) + W.range_noise(p, len(wl.t[p]), SIGMA_R)
+        probs.append(P0.with_angles(a).with_ranges(r, SIGMA_R))
+        obs.append(a)
+        ranges.append(r)
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h,
+                             obs_ranges=ranges, sigma_range=[SIGMA_R] * wl.P)
+    return wl, probs, b
+
+
+def test_range_mixed_precision_and_refinement(torch_dev):
+    """Ranged problems through the FP32 fitness, the mixed swarm and the
+    batched refinement: FP32 costs near the oracle's, reported FP64 costs and
+    chi2 equal to the oracle's at the reported states, and the refinement
+    reaching the oracle's least-squares minimum."""
+    torch, dev = torch_dev
+    wl, probs, b = ranged_batch()
+    # FP32 fitness against the oracle
+    off = iod.iod_batch_offsets(b, wl.m)
+    ld = int(off[-1])
+    xs = [W.random_swarm(20 + p, int(wl.m[p]), wl.lo[p], wl.hi[p]) for p in range(wl.P)]
+    x = torch.zeros((6, ld), dtype=torch.float64, device=dev)
+    for p in range(wl.P):
+        x[:, off[p]:off[p] + wl.m[p]] = torch.from_numpy(xs[p].T.copy()).to(dev)
+    c = torch.zeros(ld, dtype=torch.float64, device=dev)
+    iod.iod_batch_eval_f32(b, x, wl.m, c)
+    c = c.cpu().numpy()
+    for p in range(wl.P):
+        want = oracle.cost(probs[p], xs[p])
+        got = c[off[p]:off[p] + wl.m[p]]
+        big = want > 1e3
+        assert np.all(np.abs(got[big] - want[big]) <= 0.05 * want[big]), p
+    # mixed swarm, then refinement
+    params = [iod.pso_params(0.7, 1.5, 1.5, 1, wl.lo[p], wl.hi[p], problem=p) for p in range(wl.P)]
+    g, J, hist = iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=32)
+    assert np.all(np.diff(hist, axis=1) <= 0)
+    gp, chi2, Jp = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=32, n_cand=8,
+                                                n_gn=25)
+    for p in range(wl.P):
+        assert abs(J[p] - oracle.cost(probs[p], g[p][None, :])[0]) <= COST_RTOL * J[p], p
+        Pc = probs[p].with_mode(1)
+        assert abs(chi2[p] - oracle.cost(Pc, gp[p][None, :])[0]) <= COST_RTOL * chi2[p], p
+        # with ranges the refined state is within the noise of the truth
+        assert np.linalg.norm(gp[p][:3] - wl.truth[p][:3]) < 1e-5, p
