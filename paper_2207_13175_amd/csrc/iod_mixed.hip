@@ -318,25 +318,63 @@ __device__ __forceinline__ void bitonic_sort(double *key, double *idx, int n)
 // Per problem (one workgroup of TOPK_BS threads): the top_k particles with
 // the smallest (key(key[i]), i), in order, into out[p][0..top_k). Slots
 // beyond m are -1. top_k <= TOPK_BS.
+//
+// The sorted best list lives in sk/si[0, TOPK_BS); candidates collect in
+// sk/si[TOPK_BS, 2 TOPK_BS). A particle is a candidate only if it precedes
+// the list's current top_k-th entry: the list only improves, so no other
+// particle can end in the result. The buffer is merged into the list (one
+// bitonic sort of both halves) when the next chunk would overflow it, and at
+// the end. The result is the unique lexicographic top_k, so neither the
+// order in which waves append nor the merge points change it. A stream of m
+// keys yields about top_k ln(m / top_k) candidates, so a few merges replace
+// one sort per chunk.
 constexpr int TOPK_BS = 256;
 
 __global__ __launch_bounds__(TOPK_BS) void k_topk(SwarmArrays B, const double *__restrict__ keys,
                                                   int32_t top_k, int32_t *__restrict__ out)
 {
     __shared__ double sk[2 * TOPK_BS], si[2 * TOPK_BS];
+    __shared__ int n_buf, n_new;
     const int64_t p = B.porder ? B.porder[blockIdx.x] : blockIdx.x;
     const ProbDesc &D = B.desc[p];
-    const int t = threadIdx.x;
-    // running best list in [0, TOPK_BS), new chunk in [TOPK_BS, 2 TOPK_BS)
+    const int t = threadIdx.x, lane = t & 63;
     sk[t] = INFINITY;
     si[t] = INFINITY;
+    sk[TOPK_BS + t] = INFINITY;
+    si[TOPK_BS + t] = INFINITY;
+    if (t == 0) n_buf = 0;
     for (int64_t c0 = 0; c0 < D.m; c0 += TOPK_BS) {
+        if (t == 0) n_new = 0;
+        __syncthreads();   // list, buffer and counters settled
         const int64_t i = c0 + t;
-        sk[TOPK_BS + t] = i < D.m ? cost_key(keys[D.off + i]) : INFINITY;
-        si[TOPK_BS + t] = i < D.m ? (double)i : INFINITY;
-        __syncthreads();
-        bitonic_sort(sk, si, 2 * TOPK_BS);
+        const double k = i < D.m ? cost_key(keys[D.off + i]) : INFINITY;
+        const double ix = i < D.m ? (double)i : INFINITY;
+        const bool cand = i < D.m && lex_less(k, ix, sk[top_k - 1], si[top_k - 1]);
+        // slot of this candidate among the chunk's candidates
+        const uint64_t mask = __ballot(cand);
+        int base = 0;
+        if (lane == 0 && mask) base = atomicAdd(&n_new, __popcll(mask));
+        base = __shfl(base, 0, 64);
+        const int rank = base + __popcll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();   // n_new complete
+        if (n_buf + n_new > TOPK_BS) {
+            // make room: merge the buffer into the list, then empty it
+            bitonic_sort(sk, si, 2 * TOPK_BS);
+            sk[TOPK_BS + t] = INFINITY;
+            si[TOPK_BS + t] = INFINITY;
+            __syncthreads();
+            if (t == 0) n_buf = 0;
+            __syncthreads();
+        }
+        if (cand) {
+            sk[TOPK_BS + n_buf + rank] = k;
+            si[TOPK_BS + n_buf + rank] = ix;
+        }
+        __syncthreads();   // appends done before n_buf moves on
+        if (t == 0) n_buf += n_new;
     }
+    __syncthreads();
+    bitonic_sort(sk, si, 2 * TOPK_BS);
     if (t < top_k) out[p * top_k + t] = si[t] < (double)D.m ? (int32_t)si[t] : -1;
 }
 
