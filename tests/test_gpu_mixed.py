@@ -168,3 +168,34 @@ def test_mixed_top_k_all_equals_fp64_ranking_on_graph_and_eager(torch_dev):
     for o in outs[1:]:
         for a, r in zip(o, outs[0]):
             assert np.array_equal(a, r)
+
+
+def test_mixed_full_size_sampled(torch_dev):
+    """The full uneven batch (1,024 problems) in mixed precision in the
+    benchmark's launch configuration, for a few iterations: the global bests
+    are FP64 (the oracle's cost of the reported state), histories descend."""
+    wl = W.c2(0, n_iter=4)
+    probs, obs = observe(wl)
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    iod.iod_batch_set_config(b, block=64, graph=0)
+    g, J, hist = iod.iod_batch_solve_mixed(b, params_of(wl), wl.m, wl.n_iter, top_k=64)
+    assert np.all(hist[:, 1:] <= hist[:, :-1])
+    for p in range(0, wl.P, 61):
+        want = oracle.cost(probs[p], g[p][None, :])[0]
+        assert abs(J[p] - want) <= COST_RTOL * abs(want), p
+
+
+def test_refinement_full_size_sampled(torch_dev):
+    """The refinement workload's full shape (4,096 problems x 2,048
+    particles), a short swarm then the Gauss-Newton stage: reported chi2 and
+    cost are the oracle's at the reported states."""
+    wl = W.c4(0, n_iter=3)
+    probs, obs = observe(wl)
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    g, chi2, J = iod.iod_batch_solve_polished(b, params_of(wl), wl.m, wl.n_iter, top_k=64,
+                                              n_cand=16, n_gn=4)
+    for p in range(0, wl.P, 409):
+        Pc = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief[p], wl.t[p], obs[p], cost_mode=1)
+        want = oracle.cost(Pc, g[p][None, :])[0]
+        assert abs(chi2[p] - want) <= COST_RTOL * want, p
+        assert abs(J[p] - oracle.cost(probs[p], g[p][None, :])[0]) <= COST_RTOL * J[p], p
