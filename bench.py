@@ -199,14 +199,14 @@ def run_refine(args, iod, torch):
               for p in range(wl.P)]
     cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
     steps = iod.iod_batch_steps(b)
-    n_gn = args.gn_iters
+    n_gn, n_cand = args.gn_iters, args.n_cand
     for _ in range(args.warmup):
-        iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16, n_gn=n_gn)
+        iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=n_cand, n_gn=n_gn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g, chi2, J = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
-                                                  n_gn=n_gn)
+        g, chi2, J = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64,
+                                                  n_cand=n_cand, n_gn=n_gn)
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / args.steps
     iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=0)
@@ -223,8 +223,8 @@ def run_refine(args, iod, torch):
         if mult == 1:
             g64, t64 = gc, tc
     # the precision gate: the same refinement after an FP64 swarm (untimed)
-    gp64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
-                                                  n_gn=n_gn)
+    gp64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0,
+                                                  n_cand=n_cand, n_gn=n_gn)
     dpol = np.max(np.abs(g - gp64), axis=1)
     err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
     e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
@@ -235,7 +235,7 @@ def run_refine(args, iod, torch):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl.name + f"_mixed_top64_refine16x{n_gn}", "problems": wl.P,
+        "config": {"workload": wl.name + f"_mixed_top64_refine{n_cand}x{n_gn}", "problems": wl.P,
                    "particles": int(wl.m.sum()), "iterations": wl.n_iter,
                    "steps_range": [int(steps.min()), int(steps.max())],
                    "particle_steps_per_solve": ps,
@@ -369,6 +369,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
     ap.add_argument("--gn-iters", type=int, default=10,
                     help="Gauss-Newton iterations of the refinement workload")
+    ap.add_argument("--n-cand", type=int, default=16,
+                    help="personal bests refined per problem in the refinement workload")
     ap.add_argument("--variant", default="none", choices=VARIANTS,
                     help="one of the paper's variants beside Algorithm 1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
