@@ -611,20 +611,26 @@ def _make_cost_function():
 
         @staticmethod
         def forward(ctx, x, handle):
+            if x.dim() != 2 or x.shape[1] != 6:
+                raise ValueError("x must be [m, 6]")
             m = x.shape[0]
+            ctx.handle = handle
+            ctx.save_for_backward(x.detach())
+            if m == 0:
+                return x.new_zeros(0)
             ld = (m + 63) // 64 * 64
             xs = torch.zeros((6, ld), dtype=torch.float64, device=x.device)
             xs[:, :m] = x.detach().t()
             cost = torch.empty(ld, dtype=torch.float64, device=x.device)
             iod_eval_swarm(handle, xs, m, cost)
-            ctx.handle = handle
-            ctx.save_for_backward(x.detach())
             return cost[:m].clone()
 
         @staticmethod
         def backward(ctx, g):
             (x,) = ctx.saved_tensors
             m = x.shape[0]
+            if m == 0:
+                return x.new_zeros((0, 6)), None
             ld = (m + 63) // 64 * 64
             xs = torch.zeros((6, ld), dtype=torch.float64, device=x.device)
             xs[:, :m] = x.t()
