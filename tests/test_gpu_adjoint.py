@@ -217,3 +217,16 @@ def test_batch_solve_polished_mixed_matches_fp64(torch_dev):
         assert abs(c32[p] - want) <= 1e-11 * want, p
         assert abs(J32[p] - oracle.cost(probs[p], g32[p][None, :])[0]) <= 1e-11 * J32[p]
     assert np.all(diff <= 1e-9), diff
+
+
+def test_autograd_function_edge_shapes(torch_dev):
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    _, h = make(wl)
+    x = torch.zeros((0, 6), dtype=torch.float64, device=dev, requires_grad=True)
+    J = iod.iod_cost(x, h)
+    assert J.shape == (0,)
+    J.sum().backward()
+    assert x.grad.shape == (0, 6)
+    with pytest.raises(ValueError):
+        iod.iod_cost(torch.zeros((3, 5), dtype=torch.float64, device=dev), h)
