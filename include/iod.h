@@ -479,11 +479,17 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
 
 /* Swarm then refinement, for every problem of the batch: n_iter iterations of
  * the particle swarm (FP64 if top_k = 0, else mixed precision with top_k as
- * in iod_batch_solve_mixed), then n_gn Gauss-Newton iterations on each of the
- * problem's n_cand (1..64) lowest-cost personal bests, keeping the one with
- * the lowest chi2. Outputs (host): best_states [P][6], best_chi2 [P] (may be
- * NULL) and best_costs [P] (the problem's own cost mode, may be NULL).
- * Synchronous. */
+ * in iod_batch_solve_mixed), then at most n_gn damped Gauss-Newton iterations
+ * on each of the problem's n_cand (1..64) lowest-cost personal bests, keeping
+ * the one with the lowest chi2. Each iteration tries T = min(8, 64 / n_cand)
+ * dampings per candidate, lambda 10^(k - T/2) for k < T, and keeps the trial
+ * with the lowest chi2 if it is below the candidate's (lambda becomes that
+ * trial's / 10; if none is lower, 10 x the largest tried). A candidate stops
+ * once its accepted step, or every trial step when none is accepted, is at
+ * most 1e-12 in every component, or lambda reaches 1e12; a problem stops when
+ * all its candidates have. Outputs (host): best_states [P][6], best_chi2 [P]
+ * (may be NULL) and best_costs [P] (the problem's own cost mode, may be
+ * NULL). Synchronous. */
 int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,
                              int64_t n_iter, int32_t top_k, int32_t n_cand, int32_t n_gn,
                              double *best_states, double *best_chi2, double *best_costs);

@@ -1226,13 +1226,57 @@ int polish_run(const ProbDesc &d0, SwarmArrays B, int bs, int64_t grid, int32_t 
     return IOD_OK;
 }
 
+// The batched refinement loop: each iteration forms the normal equations and
+// the adjoint gradient of every live candidate, tries T dampings per
+// candidate side by side (the lanes of the problem's wave that the
+// candidates leave free), keeps the best trial, and retires problems whose
+// candidates have all stopped moving. PB holds the candidate columns
+// (p * 64 + j, j < n[p]); tdesc the trial descriptors (n[p] * T columns).
+constexpr double POLISH_STEP_TOL = 1e-12;
+
+int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
+                      const int32_t *n, int64_t P, int32_t T, int32_t n_iter, double *chi2,
+                      double *work, int32_t *active, int32_t *done, int64_t ld, hipStream_t st)
+{
+    double *jtj = work;
+    double *jtr = jtj + 21 * ld;
+    double *g = jtr + 6 * ld;
+    double *xt = g + 6 * ld;
+    double *chi2t = xt + 6 * ld;
+    double *lam = chi2t + ld;
+    double *cost = lam + ld;
+    double *adj = cost + ld;
+    double *x = PB.x;
+    PB.active = active;
+    HIP_TRY(launch_fill_cols(d0, PB, 64, P, lam, 1e-3, st));
+    SwarmArrays TB = PB;
+    TB.desc = tdesc;
+    TB.x = xt;
+    TB.cost = chi2t;
+    for (int32_t it = 0; it < n_iter; ++it) {
+        HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st));
+        SwarmArrays GB = PB;
+        GB.cost = cost;
+        HIP_TRY(launch_grad(d0, GB, 64, P, g, adj, ld, 1, st));
+        HIP_TRY(launch_gn_trials(x, jtj, g, lam, n, active, done, T, P, ld, xt, st));
+        HIP_TRY(launch_eval(d0, TB, 64, P, st));
+        HIP_TRY(launch_gn_select(x, chi2, lam, done, active, xt, chi2t, n, T, P, ld,
+                                 POLISH_STEP_TOL, st));
+    }
+    if (n_iter == 0) HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st));
+    return IOD_OK;
+}
+
 int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
                      const PolishStage &S, hipStream_t st)
 {
     const int64_t P = b->P, stride = 64, ldp = P * stride;
     int64_t rows = 0;
     for (const HostProblem &Pb : b->probs) rows = std::max(rows, adj_rows(Pb));
-    DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc;
+    // trials per candidate: the free lanes of the problem's 64-lane wave, at most 8
+    const int32_t T = std::max(1, std::min(8, 64 / S.n_cand));
+    DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc, dtdesc, dact,
+        ddone;
     HIP_TRY(hipMalloc(&dcand.p, (size_t)P * S.n_cand * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&dx.p, (size_t)6 * ldp * sizeof(double)));
     HIP_TRY(hipMalloc(&dchi.p, (size_t)ldp * sizeof(double)));
@@ -1244,11 +1288,14 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     HIP_TRY(hipMalloc(&dbest.p, (size_t)6 * P * sizeof(double)));
     HIP_TRY(hipMalloc(&dbchi.p, (size_t)P * sizeof(double)));
     HIP_TRY(hipMalloc(&dcost.p, (size_t)P * sizeof(double)));
+    HIP_TRY(hipMalloc(&dtdesc.p, (size_t)P * sizeof(ProbDesc)));
+    HIP_TRY(hipMalloc(&dact.p, (size_t)P * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&ddone.p, (size_t)ldp * sizeof(int32_t)));
     // candidates: the swarm's best personal bests
     HIP_TRY(launch_topk(B, B.jp, S.n_cand, (int32_t *)dcand.p, st));
     HIP_TRY(launch_gather(B, (const int32_t *)dcand.p, S.n_cand, (double *)dx.p, ldp, stride, st));
-    std::vector<ProbDesc> pd(L.descs), ed(L.descs);
-    std::vector<int32_t> list(2 * P), n(P);
+    std::vector<ProbDesc> pd(L.descs), ed(L.descs), td(L.descs);
+    std::vector<int32_t> list(2 * P), n(P), act(P, 1), dn0(ldp, 0);
     for (int64_t p = 0; p < P; ++p) {
         ProbDesc &D = pd[p];
         D.m = std::min<int64_t>(S.n_cand, L.descs[p].m);
@@ -1259,6 +1306,9 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
         D.hist = nullptr;
         D.hist_len = 0;
         D.k.mode = IOD_COST_CHI2;
+        td[p] = D;
+        td[p].m = D.m * T;
+        if (td[p].m > stride) return fail(IOD_EINVAL, "trial columns exceed the stride");
         ed[p] = D;
         ed[p].k.mode = L.descs[p].k.mode;
         ed[p].m = 1;
@@ -1271,6 +1321,9 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     HIP_TRY(hipMemcpyAsync(dedesc.p, ed.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dlist.p, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dn.p, n.data(), n.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dtdesc.p, td.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dact.p, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ddone.p, dn0.data(), dn0.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     SwarmArrays PB;
     std::memset(&PB, 0, sizeof PB);
     PB.desc = (const ProbDesc *)ddesc.p;
@@ -1278,7 +1331,9 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     PB.x = (double *)dx.p;
     PB.ld = ldp;
     PB.nprob = P;
-    int rc = polish_run(pd[0], PB, 64, P, S.n_gn, (double *)dchi.p, (double *)dwork.p, ldp, st);
+    int rc = polish_trials_run(pd[0], PB, (const ProbDesc *)dtdesc.p, (const int32_t *)dn.p, P, T,
+                               S.n_gn, (double *)dchi.p, (double *)dwork.p, (int32_t *)dact.p,
+                               (int32_t *)ddone.p, ldp, st);
     if (rc != IOD_OK) return rc;
     HIP_TRY(launch_pick_best((const double *)dx.p, (const double *)dchi.p, (const int32_t *)dn.p, P,
                              ldp, stride, (double *)dbest.p, (double *)dbchi.p, st));

@@ -73,6 +73,8 @@ struct SwarmArrays {
     const int32_t *porder;      // [nprob] problems by RK4 steps, longest first (per-problem
                                 // launches dispatch in this order), or null: index order
     int64_t ld, total_slots, nprob;
+    const int32_t *active = nullptr;  // [nprob]: 0 = the problem's workgroups of an evaluation,
+                                      // gradient or normal-equation launch exit at once; null: all run
 };
 
 hipError_t launch_propagate(const KArgs &A, const double *x, int64_t ld, int64_t m,
@@ -133,6 +135,18 @@ hipError_t launch_gn_accept(const ProbDesc &d0, const SwarmArrays &B, int bs, in
                             hipStream_t st);
 hipError_t launch_fill_cols(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                             double *out, double value, hipStream_t st);
+// Multi-trial damped Gauss-Newton of the batched refinement stage: one
+// 64-lane workgroup per problem p, candidate j < n[p] in column p * 64 + j,
+// its T trials (n[p] * T <= 64) in columns p * 64 + j * T + k with damping
+// lam * 10^(k - T / 2). Problems with active[p] == 0 are skipped; the select
+// step clears active[p] once none of the problem's candidates moves by more
+// than step_tol (or all sit at the damping cap).
+hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g, const double *lam,
+                            const int32_t *n, const int32_t *active, const int32_t *done,
+                            int32_t T, int64_t nprob, int64_t ld, double *xt, hipStream_t st);
+hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done, int32_t *active,
+                            const double *xt, const double *chi2t, const int32_t *n, int32_t T,
+                            int64_t nprob, int64_t ld, double step_tol, hipStream_t st);
 hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k, double *dst,
                          int64_t dld, int64_t stride, hipStream_t st);
 hipError_t launch_pick_best(const double *x, const double *chi2, const int32_t *n, int64_t nprob,

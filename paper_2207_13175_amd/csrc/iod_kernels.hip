@@ -205,6 +205,7 @@ __global__ __launch_bounds__(BS) void k_eval(ProbDesc d0, SwarmArrays B)
     __shared__ int32_t lds_ns[OBS_CHUNK];
     int64_t p, tile;
     const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    if (B.active && !B.active[p]) return;   // whole workgroup
     const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     double X[6];

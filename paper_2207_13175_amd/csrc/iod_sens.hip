@@ -227,6 +227,7 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
 {
     int64_t p, tile;
     const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    if (B.active && !B.active[p]) return;   // whole workgroup
     KArgs A = D.k;
     if (mode >= 0) A.mode = mode;
     const int64_t i = tile * BS + threadIdx.x;
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
 {
     int64_t p, tile;
     const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    if (B.active && !B.active[p]) return;   // whole workgroup
     const KArgs &A = D.k;
     const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
@@ -426,27 +428,18 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
     }
 }
 
-// Damped Gauss-Newton step per candidate (column o of B's layout): solve
-// (N + lambda diag(N)) dx = -gscale g by Cholesky (gscale g = J^T r; the
-// adjoint gives g = grad chi2 = 2 J^T r) and write the trial state x + dx.
-template <int BS, bool SINGLE>
-__global__ __launch_bounds__(BS) void k_gn_solve(ProbDesc d0, SwarmArrays B,
-                                                 const double *__restrict__ jtj,
-                                                 const double *__restrict__ g, double gscale,
-                                                 const double *__restrict__ lam,
-                                                 double *__restrict__ xt)
+// Damped Gauss-Newton step of column i: solve (N + l diag(N)) dx = -gscale g
+// by Cholesky (N = J^T J packed in jtj [21][ld]; gscale g = J^T r, the
+// adjoint giving g = grad chi2 = 2 J^T r). Returns false (dx unusable) when
+// the damped matrix is not positive definite.
+__device__ __forceinline__ bool damped_step(const double *__restrict__ jtj,
+                                            const double *__restrict__ g, int64_t ld, int64_t i,
+                                            double gscale, double l, double r[6])
 {
-    int64_t p, tile;
-    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
-    const int64_t li = tile * BS + threadIdx.x;
-    if (li >= D.m) return;
-    const int64_t i = D.off + li, ld = B.ld;
-    const double *x = B.x;
-    double M[6][6], r[6];
+    double M[6][6];
     int t = 0;
     for (int a = 0; a < 6; ++a)
         for (int b = a; b < 6; ++b, ++t) M[a][b] = M[b][a] = jtj[t * ld + i];
-    const double l = lam[i];
     for (int a = 0; a < 6; ++a) {
         M[a][a] = M[a][a] * (1.0 + l);
         r[a] = -gscale * g[a * ld + i];
@@ -475,7 +468,112 @@ __global__ __launch_bounds__(BS) void k_gn_solve(ProbDesc d0, SwarmArrays B,
         for (int c = a + 1; c < 6; ++c) v -= M[c][a] * r[c];
         r[a] = v / M[a][a];
     }
+    return ok;
+}
+
+// Damped Gauss-Newton step per candidate (column o of B's layout) with its
+// own damping lam[o]; writes the trial state x + dx (x where the step fails).
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_gn_solve(ProbDesc d0, SwarmArrays B,
+                                                 const double *__restrict__ jtj,
+                                                 const double *__restrict__ g, double gscale,
+                                                 const double *__restrict__ lam,
+                                                 double *__restrict__ xt)
+{
+    int64_t p, tile;
+    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
+    const int64_t li = tile * BS + threadIdx.x;
+    if (li >= D.m) return;
+    const int64_t i = D.off + li, ld = B.ld;
+    const double *x = B.x;
+    double r[6];
+    const bool ok = damped_step(jtj, g, ld, i, gscale, lam[i], r);
     for (int d = 0; d < 6; ++d) xt[d * ld + i] = x[d * ld + i] + (ok ? r[d] : 0.0);
+}
+
+// 10^e for a small integer e (exact for e >= 0; 1 / 10^-e below).
+__device__ __forceinline__ double pow10i(int e)
+{
+    double f = 1.0;
+    for (int k = 0; k < (e < 0 ? -e : e); ++k) f *= 10.0;
+    return e < 0 ? 1.0 / f : f;
+}
+
+// Trials of the batched refinement stage (one 64-lane workgroup per problem):
+// lane t of problem p is trial k = t % T of candidate j = t / T, damping
+// lam[j] 10^(k - T/2). A finished candidate (done) repeats its state.
+__global__ __launch_bounds__(64) void k_gn_trials(const double *__restrict__ x,
+                                                  const double *__restrict__ jtj,
+                                                  const double *__restrict__ g,
+                                                  const double *__restrict__ lam,
+                                                  const int32_t *__restrict__ n,
+                                                  const int32_t *__restrict__ active,
+                                                  const int32_t *__restrict__ done, int32_t T,
+                                                  int64_t ld, double *__restrict__ xt)
+{
+    const int64_t p = blockIdx.x;
+    if (!active[p]) return;
+    const int t = threadIdx.x, j = t / T, k = t % T;
+    if (j >= n[p]) return;
+    const int64_t c = p * 64 + j, o = p * 64 + t;
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    bool ok = false;
+    if (!done[c]) ok = damped_step(jtj, g, ld, c, 0.5, lam[c] * pow10i(k - T / 2), r);
+    for (int d = 0; d < 6; ++d) xt[d * ld + o] = x[d * ld + c] + (ok ? r[d] : 0.0);
+}
+
+// Selection after the trials: each live candidate takes its lowest trial chi2
+// (first trial on ties) if strictly below its own, and sets its damping to
+// that trial's times 0.1; if none is lower, the damping grows to 10 x the
+// largest tried. A candidate is done once its accepted step, or every trial
+// step when none is accepted, is no larger than step_tol in every component,
+// or its damping reaches the cap; the problem leaves the loop (active[p] = 0)
+// when all its candidates are done.
+__global__ __launch_bounds__(64) void k_gn_select(double *__restrict__ x, double *__restrict__ chi2,
+                                                  double *__restrict__ lam, int32_t *__restrict__ done,
+                                                  int32_t *__restrict__ active,
+                                                  const double *__restrict__ xt,
+                                                  const double *__restrict__ chi2t,
+                                                  const int32_t *__restrict__ n, int32_t T,
+                                                  int64_t ld, double step_tol)
+{
+    const int64_t p = blockIdx.x;
+    if (!active[p]) return;   // whole workgroup (one wave)
+    const int j = threadIdx.x;
+    bool live = false;
+    if (j < n[p]) {
+        const int64_t c = p * 64 + j;
+        if (!done[c]) {
+            int kb = -1;
+            double cb = chi2[c];
+            for (int k = 0; k < T; ++k) {
+                const double ct = chi2t[p * 64 + j * T + k];
+                if (ct < cb) {
+                    cb = ct;
+                    kb = k;
+                }
+            }
+            double step = 0.0;
+            if (kb >= 0) {
+                const int64_t o = p * 64 + j * T + kb;
+                for (int d = 0; d < 6; ++d) {
+                    step = fmax(step, fabs(xt[d * ld + o] - x[d * ld + c]));
+                    x[d * ld + c] = xt[d * ld + o];
+                }
+                chi2[c] = cb;
+                lam[c] = fmax(lam[c] * pow10i(kb - T / 2) * 0.1, 1e-12);
+            } else {
+                for (int k = 0; k < T; ++k)
+                    for (int d = 0; d < 6; ++d)
+                        step = fmax(step, fabs(xt[d * ld + p * 64 + j * T + k] - x[d * ld + c]));
+                lam[c] = fmin(lam[c] * pow10i(T - 1 - T / 2) * 10.0, 1e12);
+            }
+            const bool fin = !(step > step_tol) || (kb < 0 && lam[c] >= 1e12);
+            if (fin) done[c] = 1;
+            live = !fin;
+        }
+    }
+    if (!__any(live) && j == 0) active[p] = 0;
 }
 
 // Candidate gather: column (p * stride + j) of dst gets the personal best of
@@ -577,6 +675,24 @@ hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int
     const bool single = B.desc == nullptr;
     IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_gn_solve<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, jtj, g, gscale, lam, xt);
                         else hipLaunchKernelGGL((k_gn_solve<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, jtj, g, gscale, lam, xt));
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g, const double *lam,
+                            const int32_t *n, const int32_t *active, const int32_t *done,
+                            int32_t T, int64_t nprob, int64_t ld, double *xt, hipStream_t st)
+{
+    if (T < 1 || T > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gn_trials, dim3((unsigned)nprob), dim3(64), 0, st, x, jtj, g, lam, n, active, done, T, ld, xt);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done, int32_t *active,
+                            const double *xt, const double *chi2t, const int32_t *n, int32_t T,
+                            int64_t nprob, int64_t ld, double step_tol, hipStream_t st)
+{
+    if (T < 1 || T > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gn_select, dim3((unsigned)nprob), dim3(64), 0, st, x, chi2, lam, done, active, xt, chi2t, n, T, ld, step_tol);
     return hipGetLastError();
 }
 

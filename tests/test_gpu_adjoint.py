@@ -219,6 +219,37 @@ def test_batch_solve_polished_mixed_matches_fp64(torch_dev):
     assert np.all(diff <= 1e-9), diff
 
 
+def test_batch_refinement_ends_at_least_squares_minima(torch_dev):
+    """The batched refinement stage (damping trials side by side, problems
+    retired once their candidates stop moving) ends every problem at a
+    least-squares minimum: scipy's Levenberg-Marquardt, started from the
+    returned state on the oracle's residuals, moves it by at most 1e-9, and
+    the reported chi2 is the oracle's at that state. A larger iteration cap
+    moves no result by more than 1e-9."""
+    wl = W.c2(11, P=6, n_iter=30, m_range=(256, 512), K_range=(10, 24), T_range=(0.6, 1.4))
+    obs, probs = [], []
+    for p in range(wl.P):
+        P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief[p], wl.t[p], np.zeros((len(wl.t[p]), 2)),
+                            cost_mode=1)
+        a = oracle.predict(P0, wl.truth[p]) + wl.noise[p]
+        obs.append(a)
+        probs.append(P0.with_angles(a))
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, 0, wl.lo[p], wl.hi[p], problem=p)
+              for p in range(wl.P)]
+    g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=32, n_cand=16, n_gn=60)
+    g2, chi22, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=32, n_cand=16,
+                                                 n_gn=90)
+    for p in range(wl.P):
+        ref = lsq_reference(probs[p], g[p])
+        print(p, "scipy LM from the refined state moves it by", np.max(np.abs(ref - g[p])))
+        assert np.max(np.abs(ref - g[p])) <= 1e-9, p
+        want = oracle.cost(probs[p], g[p][None, :])[0]
+        assert abs(chi2[p] - want) <= 1e-11 * want, p
+    print("cap 60 vs 90: identical problems", int(np.sum(np.all(g == g2, axis=1))), "of", wl.P)
+    assert np.max(np.abs(g - g2)) <= 1e-9
+
+
 def test_autograd_function_edge_shapes(torch_dev):
     torch, dev = torch_dev
     wl = W.c0(0)
