@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
-    ap.add_argument("--gn-iters", type=int, default=40,
+    ap.add_argument("--gn-iters", type=int, default=20,
                     help="Gauss-Newton iteration cap of the refinement workload")
     ap.add_argument("--n-cand", type=int, default=16,
                     help="personal bests refined per problem in the refinement workload")

@@ -482,9 +482,11 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
  * in iod_batch_solve_mixed), then at most n_gn damped Gauss-Newton iterations
  * on each of the problem's n_cand (1..64) lowest-cost personal bests, keeping
  * the one with the lowest chi2. Each iteration tries T = min(8, 64 / n_cand)
- * dampings per candidate, lambda 10^(k - T/2) for k < T, and keeps the trial
- * with the lowest chi2 if it is below the candidate's (lambda becomes that
- * trial's / 10; if none is lower, 10 x the largest tried). A candidate stops
+ * dampings per candidate, lambda 10^(k - T/2) for k < T, each step v with its
+ * geodesic-acceleration correction a (from the residuals at x + 0.1 v) added
+ * as v + a/2 when 2|a| <= 0.75|v|, and keeps the trial with the lowest chi2
+ * if it is below the candidate's (lambda becomes that trial's / 10; if none
+ * is lower, 10 x the largest tried). A candidate stops
  * once its accepted step, or every trial step when none is accepted, is at
  * most 1e-12 in every component, or lambda reaches 1e12; a problem stops when
  * all its candidates have. Outputs (host): best_states [P][6], best_chi2 [P]

@@ -143,7 +143,15 @@ hipError_t launch_fill_cols(const ProbDesc &d0, const SwarmArrays &B, int bs, in
 // than step_tol (or all sit at the damping cap).
 hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g, const double *lam,
                             const int32_t *n, const int32_t *active, const int32_t *done,
-                            int32_t T, int64_t nprob, int64_t ld, double *xt, hipStream_t st);
+                            int32_t T, int64_t nprob, int64_t ld, double *xt, double *vt,
+                            hipStream_t st);
+// Geodesic acceleration of the trials (vt the steps, xt the trial states,
+// updated in place where the correction is accepted); descs the candidates'
+// problem descriptors, jtj / jtr the normal equations at the candidates.
+hipError_t launch_geo(const ProbDesc *descs, const double *x, const double *jtj, const double *jtr,
+                      const double *lam, const int32_t *n, const int32_t *active,
+                      const int32_t *done, int32_t T, int64_t nprob, int64_t ld, double hd,
+                      double alpha, const double *vt, double *xt, hipStream_t st);
 hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done, int32_t *active,
                             const double *xt, const double *chi2t, const int32_t *n, int32_t T,
                             int64_t nprob, int64_t ld, double step_tol, hipStream_t st);

@@ -428,13 +428,11 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
     }
 }
 
-// Damped Gauss-Newton step of column i: solve (N + l diag(N)) dx = -gscale g
-// by Cholesky (N = J^T J packed in jtj [21][ld]; gscale g = J^T r, the
-// adjoint giving g = grad chi2 = 2 J^T r). Returns false (dx unusable) when
-// the damped matrix is not positive definite.
-__device__ __forceinline__ bool damped_step(const double *__restrict__ jtj,
-                                            const double *__restrict__ g, int64_t ld, int64_t i,
-                                            double gscale, double l, double r[6])
+// Solve (N + l diag(N)) y = rhs by Cholesky, N = J^T J packed (row-major
+// upper triangle) in column i of jtj [21][ld]. Returns false (y unusable)
+// when the damped matrix is not positive definite.
+__device__ __forceinline__ bool damped_solve(const double *__restrict__ jtj, int64_t ld, int64_t i,
+                                             double l, const double rhs[6], double r[6])
 {
     double M[6][6];
     int t = 0;
@@ -442,7 +440,7 @@ __device__ __forceinline__ bool damped_step(const double *__restrict__ jtj,
         for (int b = a; b < 6; ++b, ++t) M[a][b] = M[b][a] = jtj[t * ld + i];
     for (int a = 0; a < 6; ++a) {
         M[a][a] = M[a][a] * (1.0 + l);
-        r[a] = -gscale * g[a * ld + i];
+        r[a] = rhs[a];
     }
     // Cholesky M = L L^T in place (lower triangle)
     bool ok = true;
@@ -469,6 +467,17 @@ __device__ __forceinline__ bool damped_step(const double *__restrict__ jtj,
         r[a] = v / M[a][a];
     }
     return ok;
+}
+
+// Damped Gauss-Newton step of column i: the right-hand side is -gscale g
+// (gscale g = J^T r; the adjoint gives g = grad chi2 = 2 J^T r).
+__device__ __forceinline__ bool damped_step(const double *__restrict__ jtj,
+                                            const double *__restrict__ g, int64_t ld, int64_t i,
+                                            double gscale, double l, double r[6])
+{
+    double rhs[6];
+    for (int a = 0; a < 6; ++a) rhs[a] = -gscale * g[a * ld + i];
+    return damped_solve(jtj, ld, i, l, rhs, r);
 }
 
 // Damped Gauss-Newton step per candidate (column o of B's layout) with its
@@ -509,7 +518,8 @@ __global__ __launch_bounds__(64) void k_gn_trials(const double *__restrict__ x,
                                                   const int32_t *__restrict__ n,
                                                   const int32_t *__restrict__ active,
                                                   const int32_t *__restrict__ done, int32_t T,
-                                                  int64_t ld, double *__restrict__ xt)
+                                                  int64_t ld, double *__restrict__ xt,
+                                                  double *__restrict__ vt)
 {
     const int64_t p = blockIdx.x;
     if (!active[p]) return;
@@ -519,8 +529,124 @@ __global__ __launch_bounds__(64) void k_gn_trials(const double *__restrict__ x,
     double r[6] = {0, 0, 0, 0, 0, 0};
     bool ok = false;
     if (!done[c]) ok = damped_step(jtj, g, ld, c, 0.5, lam[c] * pow10i(k - T / 2), r);
-    for (int d = 0; d < 6; ++d) xt[d * ld + o] = x[d * ld + c] + (ok ? r[d] : 0.0);
+    for (int d = 0; d < 6; ++d) {
+        vt[d * ld + o] = ok ? r[d] : 0.0;
+        xt[d * ld + o] = x[d * ld + c] + (ok ? r[d] : 0.0);
+    }
 }
+
+// Geodesic acceleration of the trial steps (Transtrum and Sethna, 2012,
+// "Improvements to the Levenberg-Marquardt algorithm for nonlinear
+// least-squares minimization"), a second-order correction along the step v:
+// with the directional second derivative of the residuals
+// r_vv ~ (2 / hd) ((r(x + hd v) - r(x)) / hd - J v), the correction solves
+// (N + l diag N) a = -J^T r_vv, and the trial becomes x + v + a / 2 when
+// 2 |a| <= alpha |v|. J^T r(x + hd v) pairs the rows of J at x (the forward
+// tangent, the same bits as the normal equations) with the residuals at
+// x + hd v; J^T r(x) and N are the normal equations' own.
+__global__ __launch_bounds__(64) void k_geo(const ProbDesc *__restrict__ descs,
+                                            const double *__restrict__ x,
+                                            const double *__restrict__ jtj,
+                                            const double *__restrict__ jtr,
+                                            const double *__restrict__ lam,
+                                            const int32_t *__restrict__ n,
+                                            const int32_t *__restrict__ active,
+                                            const int32_t *__restrict__ done, int32_t T,
+                                            int64_t ld, double hd, double alpha,
+                                            const double *__restrict__ vt, double *__restrict__ xt)
+{
+    const int64_t p = blockIdx.x;
+    if (!active[p]) return;
+    const int t = threadIdx.x, j = t / T, k = t % T;
+    if (j >= n[p]) return;
+    const int64_t c = p * 64 + j, o = p * 64 + t;
+    if (done[c]) return;
+    double v[6], vn = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        v[d] = vt[d * ld + o];
+        vn = fma(v[d], v[d], vn);
+    }
+    if (!(vn > 0.0)) return;
+    const KArgs &A = descs[p].k;
+    const double is = sqrt(A.w);
+    const bool ranged = A.wr != 0.0;
+    const double isr = sqrt(A.wr);
+    double X[6], Y[6], Phi[36], gy[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        X[d] = x[d * ld + c];
+        Y[d] = fma(hd, v[d], X[d]);
+        gy[d] = 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 36; ++d) Phi[d] = (d % 7 == 0) ? 1.0 : 0.0;
+    const int32_t S = A.ns[A.K - 1];
+    int32_t kk = 0;
+    for (int32_t st = 0; st <= S; ++st) {
+        while (kk < A.K && A.ns[kk] == st) {
+            const double *row = A.tab + (int64_t)kk * TAB_W;
+            double Sx[6], SP[36], Sy[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                Sx[d] = X[d];
+                Sy[d] = Y[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 36; ++d) SP[d] = Phi[d];
+            const double tau = row[TAB_TAU];
+            if (tau != 0.0) {
+                tangent_step(A.mu, A.mu1, tau, Sx, SP);
+                rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sy);
+            }
+            double da, db, ga[3], gb[3], dr = 0, gq[3] = {0, 0, 0};
+            double ea, eb, fa[3], fb[3], er = 0, fq[3] = {0, 0, 0};
+            bool ok = residual_and_grad(row, Sx, da, db, ga, gb, ranged, dr, gq);
+            ok = residual_and_grad(row, Sy, ea, eb, fa, fb, ranged, er, fq) && ok;
+            if (!ok) return;   // trial keeps x + v
+            const double ra = ea * is, rb = eb * is, rr = er * isr;
+#pragma unroll
+            for (int cc = 0; cc < 6; ++cc) {
+                const double ja = is * fma(ga[0], SP[cc], fma(ga[1], SP[6 + cc], ga[2] * SP[12 + cc]));
+                const double jb = is * fma(gb[0], SP[cc], fma(gb[1], SP[6 + cc], gb[2] * SP[12 + cc]));
+                gy[cc] = fma(ja, ra, fma(jb, rb, gy[cc]));
+                if (ranged) {
+                    const double jr = isr * fma(gq[0], SP[cc], fma(gq[1], SP[6 + cc], gq[2] * SP[12 + cc]));
+                    gy[cc] = fma(jr, rr, gy[cc]);
+                }
+            }
+            ++kk;
+        }
+        if (st < S) {
+            tangent_step(A.mu, A.mu1, A.h, X, Phi);
+            rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
+        }
+    }
+    // J^T r_vv = (2 / hd) ((gy - J^T r) / hd - N v)
+    double Nv[6] = {0, 0, 0, 0, 0, 0};
+    {
+        int q = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b, ++q) {
+                const double nab = jtj[q * ld + c];
+                Nv[a] = fma(nab, v[b], Nv[a]);
+                if (b != a) Nv[b] = fma(nab, v[a], Nv[b]);
+            }
+    }
+    double rhs[6], acc[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+        rhs[d] = -(2.0 / hd) * ((gy[d] - jtr[d * ld + c]) / hd - Nv[d]);
+    if (!damped_solve(jtj, ld, c, lam[c] * pow10i(k - T / 2), rhs, acc)) return;
+    double an = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) an = fma(acc[d], acc[d], an);
+    if (!(4.0 * an <= alpha * alpha * vn)) return;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) xt[d * ld + o] = x[d * ld + c] + fma(0.5, acc[d], v[d]);
+}
+
+
 
 // Selection after the trials: each live candidate takes its lowest trial chi2
 // (first trial on ties) if strictly below its own, and sets its damping to
@@ -680,10 +806,21 @@ hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int
 
 hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g, const double *lam,
                             const int32_t *n, const int32_t *active, const int32_t *done,
-                            int32_t T, int64_t nprob, int64_t ld, double *xt, hipStream_t st)
+                            int32_t T, int64_t nprob, int64_t ld, double *xt, double *vt,
+                            hipStream_t st)
 {
     if (T < 1 || T > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gn_trials, dim3((unsigned)nprob), dim3(64), 0, st, x, jtj, g, lam, n, active, done, T, ld, xt);
+    hipLaunchKernelGGL(k_gn_trials, dim3((unsigned)nprob), dim3(64), 0, st, x, jtj, g, lam, n, active, done, T, ld, xt, vt);
+    return hipGetLastError();
+}
+
+hipError_t launch_geo(const ProbDesc *descs, const double *x, const double *jtj, const double *jtr,
+                      const double *lam, const int32_t *n, const int32_t *active,
+                      const int32_t *done, int32_t T, int64_t nprob, int64_t ld, double hd,
+                      double alpha, const double *vt, double *xt, hipStream_t st)
+{
+    if (T < 1 || T > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_geo, dim3((unsigned)nprob), dim3(64), 0, st, descs, x, jtj, jtr, lam, n, active, done, T, ld, hd, alpha, vt, xt);
     return hipGetLastError();
 }
 

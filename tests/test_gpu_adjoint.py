@@ -219,13 +219,7 @@ def test_batch_solve_polished_mixed_matches_fp64(torch_dev):
     assert np.all(diff <= 1e-9), diff
 
 
-def test_batch_refinement_ends_at_least_squares_minima(torch_dev):
-    """The batched refinement stage (damping trials side by side, problems
-    retired once their candidates stop moving) ends every problem at a
-    least-squares minimum: scipy's Levenberg-Marquardt, started from the
-    returned state on the oracle's residuals, moves it by at most 1e-9, and
-    the reported chi2 is the oracle's at that state. A larger iteration cap
-    moves no result by more than 1e-9."""
+def refinement_batch():
     wl = W.c2(11, P=6, n_iter=30, m_range=(256, 512), K_range=(10, 24), T_range=(0.6, 1.4))
     obs, probs = [], []
     for p in range(wl.P):
@@ -237,6 +231,32 @@ def test_batch_refinement_ends_at_least_squares_minima(torch_dev):
     b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, 0, wl.lo[p], wl.hi[p], problem=p)
               for p in range(wl.P)]
+    return wl, b, params, probs
+
+
+@pytest.mark.parametrize("n_cand", [1, 5, 64])
+def test_batch_refinement_trial_counts(torch_dev, n_cand):
+    """Candidate counts at the ends of the range: one candidate (8 damping
+    trials), 5 (8 trials, 40 lanes) and 64 (a single trial, the plain
+    schedule). Every problem still ends at a least-squares minimum."""
+    wl, b, params, probs = refinement_batch()
+    g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=n_cand,
+                                              n_gn=60)
+    for p in range(wl.P):
+        ref = lsq_reference(probs[p], g[p])
+        assert np.max(np.abs(ref - g[p])) <= 1e-9, (n_cand, p, np.max(np.abs(ref - g[p])))
+        want = oracle.cost(probs[p], g[p][None, :])[0]
+        assert abs(chi2[p] - want) <= 1e-11 * want, p
+
+
+def test_batch_refinement_ends_at_least_squares_minima(torch_dev):
+    """The batched refinement stage (damping trials side by side, problems
+    retired once their candidates stop moving) ends every problem at a
+    least-squares minimum: scipy's Levenberg-Marquardt, started from the
+    returned state on the oracle's residuals, moves it by at most 1e-9, and
+    the reported chi2 is the oracle's at that state. A larger iteration cap
+    moves no result by more than 1e-9."""
+    wl, b, params, probs = refinement_batch()
     g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=32, n_cand=16, n_gn=60)
     g2, chi22, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=32, n_cand=16,
                                                  n_gn=90)
