@@ -119,6 +119,43 @@ def observed_angles(iod, torch, wl, with_ranges=False):
     return obs, ranges, W.SIGMA_RANGE
 
 
+def fp32_leg(iod, torch, wl, obs, x, steps_per_eval, reps=5):
+    """The same problem as a one-problem batch: FP32 (Kahan) and FP64
+    evaluations of the swarm x [6, ld] (outside the timed solve), timed with
+    HIP events on the current stream; the FP32 costs' error against FP64."""
+    b = iod.iod_create_batch([wl.mu], [wl.chief], [wl.t], [obs], [wl.sigma], h=wl.h)
+    m = np.array([wl.m], dtype=np.int64)
+    ld = x.shape[1]
+    c32 = torch.empty(ld, dtype=torch.float64, device="cuda")
+    c64 = torch.empty(ld, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, out):
+        fn(b, x, m, out, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn(b, x, m, out, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+    t32 = timed(iod.iod_batch_eval_f32, c32)
+    t64 = timed(iod.iod_batch_eval, c64)
+    iod.iod_batch_destroy(b)
+    a32, a64 = c32[:wl.m].cpu().numpy(), c64[:wl.m].cpu().numpy()
+    rel = np.abs(a32 - a64) / np.abs(a64)
+    flop = wl.m * (steps_per_eval * FLOP_PER_STEP + wl.K * FLOP_PER_OBS)
+    tf = flop / (t32 * 1e-3) / 1e12
+    return {"particle_steps_per_s": wl.m * steps_per_eval / (t32 * 1e-3), "eval_ms": t32,
+            "fp64_eval_ms": t64, "speedup_vs_fp64_eval": t64 / t32,
+            "algorithmic_tflops": tf, "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
+            "frac_of_fp32_unpacked_peak": tf / PEAK_FP64_TFLOPS,
+            "cost_rel_err_vs_fp64_q50_q99_max": [float(np.quantile(rel, 0.5)),
+                                                 float(np.quantile(rel, 0.99)), float(np.max(rel))]}
+
+
 def cpu_baseline(wl, obs, target_s):
     """Oracle fitness on chunks of the workload's particles until target_s."""
     import oracle
@@ -504,6 +541,9 @@ def main():
                      "counter_frac": (counter_tflops / PEAK_FP64_TFLOPS
                                       if counter_tflops is not None else None)},
     }
+    if args.variant == "none":
+        # the FP32 half of the metric on the same problem and swarm
+        out["fp32_eval"] = fp32_leg(iod, torch, wl, obs, sw.x, steps_per_eval)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, obs, args.cpu_seconds)
     print(json.dumps(out), flush=True)
