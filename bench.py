@@ -44,7 +44,8 @@ PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
 # sources the FP64 iteration kernel is built from
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_13175_amd", "csrc", f)
-               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
+               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")] + \
+    [os.path.join(ROOT, "paper_2207_13175_amd", "build.py")]   # its flags shape the code too
 
 
 def kernel_hash() -> str:
