@@ -94,15 +94,15 @@ __device__ __forceinline__ bool rhs(double mu, double mu1, const double s[6], do
     return !INRANGE || (D >= 0x1p-760 && D <= 0x1p1000);
 }
 
-// Classical RK4 step of size h (h2 = h/2, h6 = h/6) from X into Y. The stage
-// sum a = k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are produced,
-// so only X, a, the stage input and one derivative are live. Returns whether
-// every stage is certified.
+// Stage sum a = k1 + 2 k2 + 2 k3 + k4 of the classical RK4 step of size h
+// (h2 = h/2) from X, accumulated as the stages are produced, so only X, a,
+// the stage input and one derivative are live. Returns whether every stage
+// is certified.
 template <bool INRANGE>
-__device__ __forceinline__ bool rk4_into(double mu, double mu1, double h, double h2, double h6,
-                                         const double X[6], double Y[6])
+__device__ __forceinline__ bool rk4_sum(double mu, double mu1, double h, double h2,
+                                        const double X[6], double a[6])
 {
-    double k[6], a[6], s[6];
+    double k[6], s[6];
     bool ok = rhs<INRANGE>(mu, mu1, X, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
@@ -123,45 +123,31 @@ __device__ __forceinline__ bool rk4_into(double mu, double mu1, double h, double
     }
     ok &= rhs<INRANGE>(mu, mu1, s, k);
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        a[d] = a[d] + k[d];
-        Y[d] = fma(h6, a[d], X[d]);
-    }
+    for (int d = 0; d < 6; ++d) a[d] = a[d] + k[d];
     return ok;
 }
 
-// One RK4 step from X into Y. The step runs with the in-range sequences; if
-// any lane of the wave is not certified, the wave repeats the step from X on
-// the IEEE path. Both give the same bits wherever the first is certified, so
-// the result is always that of correctly rounded sqrt and division.
-__device__ __forceinline__ void rk4_step(double mu, double mu1, bool fast, double h, double h2,
-                                         double h6, const double X[6], double Y[6])
-{
-    bool ok = false;
-    if (fast) ok = rk4_into<true>(mu, mu1, h, h2, h6, X, Y);
-    if (!__all(ok)) rk4_into<false>(mu, mu1, h, h2, h6, X, Y);
-}
-
-// One RK4 step in place.
+// One RK4 step in place, X <- X + h6 a (h6 = h/6). The stage sum runs with
+// the in-range sequences; if any lane of the wave is not certified, the wave
+// recomputes it from X on the IEEE path. Both give the same bits wherever the
+// first is certified, so the result is always that of correctly rounded
+// sqrt and division. X is updated only once the sum is final, so nothing
+// needs a second copy of the state.
 __device__ __forceinline__ void rk4(double mu, double mu1, bool fast, double h, double h2,
                                     double h6, double X[6])
 {
-    double Y[6];
-    rk4_step(mu, mu1, fast, h, h2, h6, X, Y);
+    double a[6];
+    bool ok = false;
+    if (fast) ok = rk4_sum<true>(mu, mu1, h, h2, X, a);
+    if (!__all(ok)) rk4_sum<false>(mu, mu1, h, h2, X, a);
 #pragma unroll
-    for (int d = 0; d < 6; ++d) X[d] = Y[d];
+    for (int d = 0; d < 6; ++d) X[d] = fma(h6, a[d], X[d]);
 }
 
-// n steps of size h in place, two at a time between two register sets so
-// that no copy is needed between steps.
+// n steps of size h in place.
 __device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6])
 {
-    double Y[6];
-    for (; n >= 2; n -= 2) {
-        rk4_step(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X, Y);
-        rk4_step(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y, X);
-    }
-    if (n == 1) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
+    for (; n > 0; --n) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
 }
 
 // Walk the observation schedule: advance X on the grid, and at each
