@@ -1239,9 +1239,10 @@ constexpr double GEO_ALPHA = 0.75;  // accept the correction a if 2 |a| <= alpha
 
 int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
                       const int32_t *n, int64_t P, int32_t T, int32_t n_iter, double *chi2,
-                      double *work, double *vt, int32_t *active, int32_t *done, int64_t ld,
-                      hipStream_t st)
+                      double *work, double *vt, double *jrows, int32_t n_cand, int32_t *active,
+                      int32_t *done, int64_t ld, hipStream_t st)
 {
+    const int64_t jld = P * n_cand;
     double *jtj = work;
     double *jtr = jtj + 21 * ld;
     double *g = jtr + 6 * ld;
@@ -1258,13 +1259,13 @@ int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
     TB.x = xt;
     TB.cost = chi2t;
     for (int32_t it = 0; it < n_iter; ++it) {
-        HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st));
+        HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st, jrows, n_cand, jld));
         SwarmArrays GB = PB;
         GB.cost = cost;
         HIP_TRY(launch_grad(d0, GB, 64, P, g, adj, ld, 1, st));
         HIP_TRY(launch_gn_trials(x, jtj, g, lam, n, active, done, T, P, ld, xt, vt, st));
-        HIP_TRY(launch_geo(PB.desc, x, jtj, jtr, lam, n, active, done, T, P, ld, GEO_HD, GEO_ALPHA,
-                           vt, xt, st));
+        HIP_TRY(launch_geo(PB.desc, x, jtj, jtr, jrows, n_cand, jld, lam, n, active, done, T, P,
+                           ld, GEO_HD, GEO_ALPHA, vt, xt, st));
         HIP_TRY(launch_eval(d0, TB, 64, P, st));
         HIP_TRY(launch_gn_select(x, chi2, lam, done, active, xt, chi2t, n, T, P, ld,
                                  POLISH_STEP_TOL, st));
@@ -1282,7 +1283,11 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     // trials per candidate: the free lanes of the problem's 64-lane wave, at most 8
     const int32_t T = std::max(1, std::min(8, 64 / S.n_cand));
     DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc, dtdesc, dact,
-        ddone, dvt;
+        ddone, dvt, djrows;
+    // rows of J of every candidate: max over problems of K R (R = 3 with ranges, else 2)
+    int64_t jrow_max = 0;
+    for (const HostProblem &Pb : b->probs)
+        jrow_max = std::max<int64_t>(jrow_max, (int64_t)Pb.K * (Pb.sigma_range > 0 ? 3 : 2));
     HIP_TRY(hipMalloc(&dcand.p, (size_t)P * S.n_cand * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&dx.p, (size_t)6 * ldp * sizeof(double)));
     HIP_TRY(hipMalloc(&dchi.p, (size_t)ldp * sizeof(double)));
@@ -1298,6 +1303,7 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     HIP_TRY(hipMalloc(&dact.p, (size_t)P * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&ddone.p, (size_t)ldp * sizeof(int32_t)));
     HIP_TRY(hipMalloc(&dvt.p, (size_t)6 * ldp * sizeof(double)));
+    HIP_TRY(hipMalloc(&djrows.p, (size_t)jrow_max * 6 * P * S.n_cand * sizeof(double)));
     // candidates: the swarm's best personal bests
     HIP_TRY(launch_topk(B, B.jp, S.n_cand, (int32_t *)dcand.p, st));
     HIP_TRY(launch_gather(B, (const int32_t *)dcand.p, S.n_cand, (double *)dx.p, ldp, stride, st));
@@ -1340,7 +1346,8 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     PB.nprob = P;
     int rc = polish_trials_run(pd[0], PB, (const ProbDesc *)dtdesc.p, (const int32_t *)dn.p, P, T,
                                S.n_gn, (double *)dchi.p, (double *)dwork.p, (double *)dvt.p,
-                               (int32_t *)dact.p, (int32_t *)ddone.p, ldp, st);
+                               (double *)djrows.p, S.n_cand, (int32_t *)dact.p,
+                               (int32_t *)ddone.p, ldp, st);
     if (rc != IOD_OK) return rc;
     HIP_TRY(launch_pick_best((const double *)dx.p, (const double *)dchi.p, (const int32_t *)dn.p, P,
                              ldp, stride, (double *)dbest.p, (double *)dbchi.p, st));

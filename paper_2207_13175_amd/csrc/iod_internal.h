@@ -123,9 +123,12 @@ hipError_t launch_reeval64(const SwarmArrays &B, const int32_t *cand, int32_t to
 constexpr int ADJ_CKPT = 64;
 hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                        double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st);
-// chi2 [ld], jtj [21][ld], jtr [6][ld] of the whitened residuals.
+// chi2 [ld], jtj [21][ld], jtr [6][ld] of the whitened residuals. With
+// jrows, also the rows of J: observation k's residual r (R = 2, or 3 with
+// ranges) of particle i of problem p at jrows[((k R + r) 6 + c) jld + p jstride + i].
 hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                         double *chi2, double *jtj, double *jtr, hipStream_t st);
+                         double *chi2, double *jtj, double *jtr, hipStream_t st,
+                         double *jrows = nullptr, int64_t jstride = 0, int64_t jld = 0);
 // Per-column Gauss-Newton step (on B.x) and acceptance, over B's layout.
 hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                            const double *jtj, const double *g, double gscale, const double *lam,
@@ -147,11 +150,14 @@ hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g,
                             hipStream_t st);
 // Geodesic acceleration of the trials (vt the steps, xt the trial states,
 // updated in place where the correction is accepted); descs the candidates'
-// problem descriptors, jtj / jtr the normal equations at the candidates.
+// problem descriptors, jtj / jtr the normal equations at the candidates and
+// jrows their rows of J (launch_normal's layout, candidate j of problem p in
+// column p jstride + j).
 hipError_t launch_geo(const ProbDesc *descs, const double *x, const double *jtj, const double *jtr,
-                      const double *lam, const int32_t *n, const int32_t *active,
-                      const int32_t *done, int32_t T, int64_t nprob, int64_t ld, double hd,
-                      double alpha, const double *vt, double *xt, hipStream_t st);
+                      const double *jrows, int64_t jstride, int64_t jld, const double *lam,
+                      const int32_t *n, const int32_t *active, const int32_t *done, int32_t T,
+                      int64_t nprob, int64_t ld, double hd, double alpha, const double *vt,
+                      double *xt, hipStream_t st);
 hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done, int32_t *active,
                             const double *xt, const double *chi2t, const int32_t *n, int32_t T,
                             int64_t nprob, int64_t ld, double step_tol, hipStream_t st);

@@ -350,7 +350,9 @@ __device__ __forceinline__ void tangent_step(double mu, double mu1, double h, do
 
 template <int BS, bool SINGLE>
 __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, double *__restrict__ chi2,
-                                               double *__restrict__ jtj, double *__restrict__ jtr)
+                                               double *__restrict__ jtj, double *__restrict__ jtr,
+                                               double *__restrict__ jrows, int64_t jstride,
+                                               int64_t jld)
 {
     int64_t p, tile;
     const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
@@ -394,6 +396,17 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
                 ja[c] = is * fma(ga[0], SP[c], fma(ga[1], SP[6 + c], ga[2] * SP[12 + c]));
                 jb[c] = is * fma(gb[0], SP[c], fma(gb[1], SP[6 + c], gb[2] * SP[12 + c]));
                 jr[c] = isr * fma(gq[0], SP[c], fma(gq[1], SP[6 + c], gq[2] * SP[12 + c]));
+            }
+            if (jrows && valid) {
+                // rows of J for this observation: (k R + r) 6 + c, column p jstride + i
+                const int R = ranged ? 3 : 2;
+                double *q = jrows + (int64_t)k * R * 6 * jld + p * jstride + i;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    q[c * jld] = ja[c];
+                    q[(6 + c) * jld] = jb[c];
+                    if (ranged) q[(12 + c) * jld] = jr[c];
+                }
             }
             const double ra = da * is, rb = db * is, rr = dr * isr;
             c2 = fma(ra, ra, fma(rb, rb, c2));
@@ -541,14 +554,15 @@ __global__ __launch_bounds__(64) void k_gn_trials(const double *__restrict__ x,
 // with the directional second derivative of the residuals
 // r_vv ~ (2 / hd) ((r(x + hd v) - r(x)) / hd - J v), the correction solves
 // (N + l diag N) a = -J^T r_vv, and the trial becomes x + v + a / 2 when
-// 2 |a| <= alpha |v|. J^T r(x + hd v) pairs the rows of J at x (the forward
-// tangent, the same bits as the normal equations) with the residuals at
-// x + hd v; J^T r(x) and N are the normal equations' own.
+// 2 |a| <= alpha |v|. J^T r(x + hd v) pairs the rows of J at x, stored by the
+// normal-equation launch (jrows, column p jstride + j), with the residuals
+// propagated from x + hd v; J^T r(x) and N are the normal equations' own.
 __global__ __launch_bounds__(64) void k_geo(const ProbDesc *__restrict__ descs,
                                             const double *__restrict__ x,
                                             const double *__restrict__ jtj,
                                             const double *__restrict__ jtr,
-                                            const double *__restrict__ lam,
+                                            const double *__restrict__ jrows, int64_t jstride,
+                                            int64_t jld, const double *__restrict__ lam,
                                             const int32_t *__restrict__ n,
                                             const int32_t *__restrict__ active,
                                             const int32_t *__restrict__ done, int32_t T,
@@ -571,64 +585,45 @@ __global__ __launch_bounds__(64) void k_geo(const ProbDesc *__restrict__ descs,
     const KArgs &A = descs[p].k;
     const double is = sqrt(A.w);
     const bool ranged = A.wr != 0.0;
+    const int R = ranged ? 3 : 2;
     const double isr = sqrt(A.wr);
-    double X[6], Y[6], Phi[36], gy[6];
+    const double *rows = jrows + p * jstride + j;
+    double Y[6], gy[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-        X[d] = x[d * ld + c];
-        Y[d] = fma(hd, v[d], X[d]);
+        Y[d] = fma(hd, v[d], x[d * ld + c]);
         gy[d] = 0.0;
     }
-#pragma unroll
-    for (int d = 0; d < 36; ++d) Phi[d] = (d % 7 == 0) ? 1.0 : 0.0;
     const int32_t S = A.ns[A.K - 1];
     int32_t kk = 0;
     for (int32_t st = 0; st <= S; ++st) {
         while (kk < A.K && A.ns[kk] == st) {
             const double *row = A.tab + (int64_t)kk * TAB_W;
-            double Sx[6], SP[36], Sy[6];
+            double Sy[6];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) {
-                Sx[d] = X[d];
-                Sy[d] = Y[d];
-            }
-#pragma unroll
-            for (int d = 0; d < 36; ++d) SP[d] = Phi[d];
+            for (int d = 0; d < 6; ++d) Sy[d] = Y[d];
             const double tau = row[TAB_TAU];
-            if (tau != 0.0) {
-                tangent_step(A.mu, A.mu1, tau, Sx, SP);
-                rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sy);
-            }
-            double da, db, ga[3], gb[3], dr = 0, gq[3] = {0, 0, 0};
+            if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sy);
             double ea, eb, fa[3], fb[3], er = 0, fq[3] = {0, 0, 0};
-            bool ok = residual_and_grad(row, Sx, da, db, ga, gb, ranged, dr, gq);
-            ok = residual_and_grad(row, Sy, ea, eb, fa, fb, ranged, er, fq) && ok;
-            if (!ok) return;   // trial keeps x + v
+            if (!residual_and_grad(row, Sy, ea, eb, fa, fb, ranged, er, fq)) return;   // keeps x + v
             const double ra = ea * is, rb = eb * is, rr = er * isr;
+            const double *q = rows + (int64_t)kk * R * 6 * jld;
 #pragma unroll
             for (int cc = 0; cc < 6; ++cc) {
-                const double ja = is * fma(ga[0], SP[cc], fma(ga[1], SP[6 + cc], ga[2] * SP[12 + cc]));
-                const double jb = is * fma(gb[0], SP[cc], fma(gb[1], SP[6 + cc], gb[2] * SP[12 + cc]));
-                gy[cc] = fma(ja, ra, fma(jb, rb, gy[cc]));
-                if (ranged) {
-                    const double jr = isr * fma(gq[0], SP[cc], fma(gq[1], SP[6 + cc], gq[2] * SP[12 + cc]));
-                    gy[cc] = fma(jr, rr, gy[cc]);
-                }
+                gy[cc] = fma(q[cc * jld], ra, fma(q[(6 + cc) * jld], rb, gy[cc]));
+                if (ranged) gy[cc] = fma(q[(12 + cc) * jld], rr, gy[cc]);
             }
             ++kk;
         }
-        if (st < S) {
-            tangent_step(A.mu, A.mu1, A.h, X, Phi);
-            rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
-        }
+        if (st < S) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
     }
     // J^T r_vv = (2 / hd) ((gy - J^T r) / hd - N v)
     double Nv[6] = {0, 0, 0, 0, 0, 0};
     {
-        int q = 0;
+        int qi = 0;
         for (int a = 0; a < 6; ++a)
-            for (int b = a; b < 6; ++b, ++q) {
-                const double nab = jtj[q * ld + c];
+            for (int b = a; b < 6; ++b, ++qi) {
+                const double nab = jtj[qi * ld + c];
                 Nv[a] = fma(nab, v[b], Nv[a]);
                 if (b != a) Nv[b] = fma(nab, v[a], Nv[b]);
             }
@@ -645,8 +640,6 @@ __global__ __launch_bounds__(64) void k_geo(const ProbDesc *__restrict__ descs,
 #pragma unroll
     for (int d = 0; d < 6; ++d) xt[d * ld + o] = x[d * ld + c] + fma(0.5, acc[d], v[d]);
 }
-
-
 
 // Selection after the trials: each live candidate takes its lowest trial chi2
 // (first trial on ties) if strictly below its own, and sets its damping to
@@ -786,13 +779,15 @@ hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t
 }
 
 hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                         double *chi2, double *jtj, double *jtr, hipStream_t st)
+                         double *chi2, double *jtj, double *jtr, hipStream_t st, double *jrows,
+                         int64_t jstride, int64_t jld)
 {
     const bool single = B.desc == nullptr;
-    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_normal<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr);
-                        else hipLaunchKernelGGL((k_normal<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr));
+    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_normal<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr, jrows, jstride, jld);
+                        else hipLaunchKernelGGL((k_normal<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr, jrows, jstride, jld));
     return hipGetLastError();
 }
+
 
 hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                            const double *jtj, const double *g, double gscale, const double *lam,
@@ -815,12 +810,13 @@ hipError_t launch_gn_trials(const double *x, const double *jtj, const double *g,
 }
 
 hipError_t launch_geo(const ProbDesc *descs, const double *x, const double *jtj, const double *jtr,
-                      const double *lam, const int32_t *n, const int32_t *active,
-                      const int32_t *done, int32_t T, int64_t nprob, int64_t ld, double hd,
-                      double alpha, const double *vt, double *xt, hipStream_t st)
+                      const double *jrows, int64_t jstride, int64_t jld, const double *lam,
+                      const int32_t *n, const int32_t *active, const int32_t *done, int32_t T,
+                      int64_t nprob, int64_t ld, double hd, double alpha, const double *vt,
+                      double *xt, hipStream_t st)
 {
-    if (T < 1 || T > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_geo, dim3((unsigned)nprob), dim3(64), 0, st, descs, x, jtj, jtr, lam, n, active, done, T, ld, hd, alpha, vt, xt);
+    if (T < 1 || T > 64 || !jrows) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_geo, dim3((unsigned)nprob), dim3(64), 0, st, descs, x, jtj, jtr, jrows, jstride, jld, lam, n, active, done, T, ld, hd, alpha, vt, xt);
     return hipGetLastError();
 }
 
