@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "../../include/iod.h"
-#include "iod_internal.h"
+#include "iod_launch.h"
 
 using namespace iodk;
 

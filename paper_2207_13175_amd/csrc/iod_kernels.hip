@@ -34,6 +34,7 @@
 // kernels; the building blocks are in iod_device.h, the mixed-precision
 // kernels in iod_mixed.hip and the sensitivity kernels in iod_sens.hip.
 #include "iod_device.h"
+#include "iod_launch.h"
 
 namespace iodk {
 

@@ -5,6 +5,7 @@
 // on those FP64 costs. A systems variant: the paper works in double
 // precision throughout.
 #include "iod_device.h"
+#include "iod_launch.h"
 
 namespace iodk {
 

@@ -6,6 +6,7 @@
 // Levenberg-Marquardt Local Minimization, eqs. non:linear:lsq and
 // nonlinlsq:cost).
 #include "iod_device.h"
+#include "iod_launch.h"
 
 namespace iodk {
 
