@@ -44,15 +44,18 @@ PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
 # sources the FP64 iteration kernel is built from
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_13175_amd", "csrc", f)
-               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")] + \
-    [os.path.join(ROOT, "paper_2207_13175_amd", "build.py")]   # its flags shape the code too
+               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
 
 
 def kernel_hash() -> str:
+    """Hash of what shapes the iteration kernel's code: its sources and the
+    compiler flags of its file."""
+    from paper_2207_13175_amd import build as B
     h = hashlib.sha256()
     for path in KERNEL_SRCS:
         with open(path, "rb") as f:
             h.update(f.read())
+    h.update(repr(B.ARCH + B.FLAGS + dict(B.UNITS)["iod_kernels.hip"]).encode())
     return h.hexdigest()[:16]
 
 
