@@ -139,3 +139,17 @@ def test_pso_params_layout_matches_header():
     p = iod.pso_params(0.7, 2.05, 2.05, 3, np.zeros(6), np.ones(6), problem=2,
                        flags=iod.IOD_PSO_CONSTRICTION | iod.IOD_PSO_GRID_INIT, tol=1e-4, tol_lag=7)
     assert p.flags == 5 and p.tol_lag == 7 and p.tol == 1e-4 and p.problem == 2
+
+
+def test_build_compiles_every_kernel_source():
+    """Every .hip file under csrc is one compile unit of the library (a file
+    left out would drop its entry points), and the FP32 kernels' file keeps
+    the default scheduler (the latency-oriented one would cut its occupancy)."""
+    import glob
+    import os
+    from paper_2207_13175_amd import build as B
+    on_disk = sorted(os.path.basename(f) for f in glob.glob(os.path.join(B.CSRC, "*.hip")))
+    assert sorted(f for f, _ in B.UNITS) == on_disk
+    assert dict(B.UNITS)["iod_mixed.hip"] == []
+    assert "-ffp-contract=off" in B.FLAGS
+    assert "-packed-fp32-ops" in B.FLAGS
