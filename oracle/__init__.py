@@ -97,6 +97,8 @@ def _load():
     lib.orc_residuals_per_obs.restype = C.c_int
     lib.orc_cost.argtypes = [C.POINTER(_Problem), C.c_int64, _D, _D]
     lib.orc_cost.restype = C.c_int
+    lib.orc_cost_ld.argtypes = [C.POINTER(_Problem), C.c_int64, _D, _D]
+    lib.orc_cost_ld.restype = C.c_int
     lib.orc_philox4x64.argtypes = [_U64, _U64, _U64]
     lib.orc_pso_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Pso), C.c_int64,
                                  _D, _D, _D, _D, _D, _D, _D, _I64]
@@ -273,6 +275,18 @@ def cost(problem: Problem, x):
     x = _f64(x).reshape(-1, 6)
     out = np.empty(len(x))
     if lib.orc_cost(C.byref(problem._s), len(x), _dp(x), _dp(out)) != 0:
+        raise ValueError("invalid problem")
+    return out
+
+
+def cost_ld(problem: Problem, x):
+    """Accuracy reference: costs [m] of particles x [m, 6] from the same
+    discrete method evaluated in x87 extended precision with the paper's
+    literal formulas (not the binary64 arithmetic contract)."""
+    lib = _load()
+    x = _f64(x).reshape(-1, 6)
+    out = np.empty(len(x))
+    if lib.orc_cost_ld(C.byref(problem._s), len(x), _dp(x), _dp(out)) != 0:
         raise ValueError("invalid problem")
     return out
 

@@ -40,7 +40,9 @@
  * constants and period ratios, literal-formula angle residuals in extended
  * precision, noise statistics of the cost, a brute-force grid minimum, the
  * PSO invariants and isolated velocity-update terms, Philox bit patterns
- * from numpy; for the variants: chi-square statistics with ranges, the
+ * from numpy, an extended-precision evaluation of the same method from the
+ * literal formulas (orc_cost_ld, which also states the true accuracy of the
+ * binary64 cost); for the variants: chi-square statistics with ranges, the
  * published constriction value and its quadratic identity, the Cartesian
  * cell-centre lattice, and Algorithm 2's stop index recomputed from an
  * untruncated run).
@@ -437,6 +439,122 @@ int orc_cost(const orc_problem *P, int64_t m, const double *x, double *cost)
     for (i = 0; i < m; i++) cost[i] = cost_one(P, &T, x + 6 * i);
     tables_free(&T);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accuracy reference. The same discrete method -- classical RK4 with the    */
+/* same step, schedule and partial steps, the chief propagated alike, the    */
+/* same cost -- evaluated in x87 extended precision (long double, 64-bit     */
+/* significand) from the paper's literal formulas: 1/r^3 as written in the   */
+/* equations of motion, L = rho/|rho|, azimuth atan2(L_y, L_x) with the      */
+/* residual wrapped to (-pi, pi], elevation asin(L_z). It is not part of the */
+/* arithmetic contract that the GPU library shares with the binary64 code    */
+/* above; it measures how far that binary64 result is from the exact value  */
+/* of the discrete method, which the 1e-11 parity bar does not.              */
+/* ------------------------------------------------------------------------ */
+
+typedef long double ld;
+
+static const ld PI_LD = 3.14159265358979323846264338327950288L;
+
+/* Equations of motion, eqs. (cr3bp:x), (cr3bp:y), (cr3bp:z), written out. */
+static void rhs_ld(ld mu, const ld s[6], ld f[6])
+{
+    const ld x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4], vz = s[5];
+    const ld r1 = sqrtl((x + mu) * (x + mu) + y * y + z * z);
+    const ld r2 = sqrtl((x - 1 + mu) * (x - 1 + mu) + y * y + z * z);
+    const ld g1 = (1 - mu) / (r1 * r1 * r1), g2 = mu / (r2 * r2 * r2);
+    f[0] = vx;
+    f[1] = vy;
+    f[2] = vz;
+    f[3] = 2 * vy + x - g1 * (x + mu) - g2 * (x - 1 + mu);
+    f[4] = -2 * vx + y - g1 * y - g2 * y;
+    f[5] = -g1 * z - g2 * z;
+}
+
+/* Classical RK4: X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4). */
+static void rk4_ld(ld mu, ld h, ld X[6])
+{
+    ld k1[6], k2[6], k3[6], k4[6], s[6];
+    int d;
+    rhs_ld(mu, X, k1);
+    for (d = 0; d < 6; d++) s[d] = X[d] + h / 2 * k1[d];
+    rhs_ld(mu, s, k2);
+    for (d = 0; d < 6; d++) s[d] = X[d] + h / 2 * k2[d];
+    rhs_ld(mu, s, k3);
+    for (d = 0; d < 6; d++) s[d] = X[d] + h * k3[d];
+    rhs_ld(mu, s, k4);
+    for (d = 0; d < 6; d++) X[d] = X[d] + h / 6 * (k1[d] + 2 * k2[d] + 2 * k3[d] + k4[d]);
+}
+
+/* States at the observation times in extended precision; out is [K][6]. */
+static void propagate_ld(ld mu, ld h, const double x0[6], int32_t K, const int64_t *ns,
+                         const double *tau, ld *out)
+{
+    ld X[6];
+    int64_t step = 0;
+    int32_t k;
+    int d;
+    for (d = 0; d < 6; d++) X[d] = x0[d];
+    for (k = 0; k < K; k++) {
+        ld S[6];
+        while (step < ns[k]) {
+            rk4_ld(mu, h, X);
+            step++;
+        }
+        for (d = 0; d < 6; d++) S[d] = X[d];
+        if (tau[k] != 0.0) rk4_ld(mu, (ld)tau[k], S);
+        for (d = 0; d < 6; d++) out[6 * (int64_t)k + d] = S[d];
+    }
+}
+
+/* Costs of m particles (x is [m][6]) in extended precision, rounded to
+ * binary64 on return; the same problem definition and modes as orc_cost. */
+int orc_cost_ld(const orc_problem *P, int64_t m, const double *x, double *cost)
+{
+    const int32_t K = P->n_obs;
+    int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)K);
+    ld *chief = (ld *)malloc(sizeof(ld) * 6 * (size_t)K);
+    int64_t i;
+    int rc = orc_schedule(P->t, K, P->h, ns, tau);
+    if (rc == 0) {
+        const ld mu = P->mu, h = P->h;
+        const ld w = 1 / ((ld)P->sigma * (ld)P->sigma);
+        const ld wr = P->ranges ? 1 / ((ld)P->sigma_range * (ld)P->sigma_range) : 0;
+        propagate_ld(mu, h, P->chief, K, ns, tau, chief);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (i = 0; i < m; i++) {
+            ld *st = (ld *)malloc(sizeof(ld) * 6 * (size_t)K);
+            ld J = 0;
+            int32_t k;
+            propagate_ld(mu, h, x + 6 * i, K, ns, tau, st);
+            for (k = 0; k < K; k++) {
+                const ld rx = st[6 * k] - chief[6 * k], ry = st[6 * k + 1] - chief[6 * k + 1];
+                const ld rz = st[6 * k + 2] - chief[6 * k + 2];
+                const ld r = sqrtl(rx * rx + ry * ry + rz * rz);
+                ld e, da, db;
+                if (r == 0) {
+                    e = INFINITY;
+                } else {
+                    da = (ld)P->angles[2 * k] - atan2l(ry / r, rx / r);
+                    while (da > PI_LD) da -= 2 * PI_LD;
+                    while (da <= -PI_LD) da += 2 * PI_LD;
+                    db = (ld)P->angles[2 * k + 1] - asinl(rz / r);
+                    e = w * (da * da + db * db);
+                    if (P->ranges) {
+                        const ld dr = (ld)P->ranges[k] - r;
+                        e += wr * dr * dr;
+                    }
+                }
+                J = (P->cost_mode == ORC_COST_CHI2) ? J + e : J + e * e;
+            }
+            cost[i] = (double)J;
+            free(st);
+        }
+    }
+    free(ns); free(tau); free(chief);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

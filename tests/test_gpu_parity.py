@@ -389,3 +389,32 @@ def test_maximum_observation_count(torch_dev):
     got = st.cpu().numpy()
     for i in range(3):
         assert np.array_equal(got[:, :, i], oracle.propagate(wl.mu, h, xs[i], t)), i
+
+
+@pytest.mark.parametrize("which", ["c0", "c1"])
+def test_cost_accuracy_against_extended_precision(torch_dev, which):
+    """The true accuracy of the GPU's binary64 costs, which the 1e-11 parity
+    bar does not measure: against the oracle's extended-precision evaluation
+    of the same discrete method (literal formulas, no shared arithmetic),
+    median <= 1e-9 away from the minimum and <= 1e-6 at the noise floor (the
+    binary64 angles carry ~1e-12 rad from the deputy-chief cancellation,
+    against residuals of sigma = 1e-5 rad). The FP32 ranking costs of the
+    same particles are stated beside them."""
+    torch, dev = torch_dev
+    wl = W.c0(0) if which == "c0" else W.c1(0)
+    P, obs = make_problem(wl)
+    xs = W.random_swarm(9, 64, wl.lo, wl.hi)
+    xs[0] = wl.truth
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    got = gpu_cost(torch, dev, h, xs)
+    ref = oracle.cost_ld(P, xs)
+    rel = np.abs(got - ref) / np.abs(ref)
+    b = iod.iod_create_batch([wl.mu], [wl.chief], [wl.t], [obs], [wl.sigma], h=wl.h)
+    x = to_dev(torch, dev, xs)
+    c32 = torch.zeros(x.shape[1], dtype=torch.float64, device=dev)
+    iod.iod_batch_eval_f32(b, x, np.array([len(xs)]), c32)
+    rel32 = np.abs(c32.cpu().numpy()[:len(xs)] - ref) / np.abs(ref)
+    print(f"{which}: FP64 vs extended precision median {np.median(rel):.2e} max {rel.max():.2e}; "
+          f"FP32 median {np.median(rel32):.2e} max {rel32.max():.2e}")
+    assert np.median(rel[1:]) <= 1e-9
+    assert rel.max() <= 1e-6

@@ -334,6 +334,34 @@ def test_zero_cost_at_truth_noise_free(orc):
         assert J2 > 1e-6
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_binary64_cost_against_extended_precision(orc, mode):
+    """The binary64 contract against the same discrete method evaluated in
+    x87 extended precision from the paper's literal formulas (1/r^3 as
+    written, L = rho/|rho|, atan2/asin, wrapped azimuth). The two share no
+    arithmetic, so a dropped term, a sign or an index slip in either shows
+    up at O(1). What remains is binary64 rounding: |rho| ~ 1e-3 of |r| ~ 1
+    costs three digits in rho, a ~1e-12 rad error in the angles. Away from
+    the minimum (residuals >> sigma) that is ~1e-12 of the cost; at the noise
+    floor (residuals ~ sigma = 1e-5 rad) the relative error of e_k is
+    ~2e-12 / 1e-5 = 2e-7, and 4e-7 for e_k^2: the bar there is 1e-6."""
+    wl = W.c0(0)
+    P0 = orc.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((wl.K, 2)), mode)
+    P = P0.with_angles(orc.predict(P0, wl.truth) + wl.noise)
+    xs = W.random_swarm(5, 96, wl.lo, wl.hi)
+    xs[0] = wl.truth
+    J, Jl = orc.cost(P, xs), orc.cost_ld(P, xs)
+    rel = np.abs(J - Jl) / np.abs(Jl)
+    print("binary64 vs extended precision: median %.2e, at the truth %.2e" % (np.median(rel), rel[0]))
+    assert np.median(rel[1:]) <= 1e-10
+    assert np.max(rel) <= 1e-6
+    # noise-free data: the extended-precision cost at the truth is the
+    # binary64 angles' own rounding, residuals ~1e-12 rad, far below sigma
+    Pn = noise_free_problem(orc, wl, mode)
+    Jt = orc.cost_ld(Pn, wl.truth[None, :])[0]
+    assert 0.0 <= Jt <= (wl.K * 2e-14 if mode == 1 else 1e-24), Jt
+
+
 def test_cost_is_infinite_on_the_chief(orc):
     wl = W.tiny(0)
     P = noise_free_problem(orc, wl)
