@@ -35,6 +35,7 @@ UNITS = [("iod_kernels.hip", MAX_ILP), ("iod_mixed.hip", []), ("iod_sens.hip", [
 SOURCES = [os.path.join(CSRC, f) for f, _ in UNITS]
 
 ARCH = ["--offload-arch=gfx950"]
+LIBS = ["-lrocprofiler-sdk-roctx"]   # phase ranges for marker-recording tools
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-command-line-argument"]
@@ -65,7 +66,7 @@ def build(verbose: bool = False) -> str:
         text = _run_all([[hipcc(), *ARCH, *FLAGS, *extra, "-c", "-o", o, os.path.join(CSRC, f)]
                          for (f, extra), o in zip(UNITS, objs)])
         tmp = LIB + ".tmp"
-        text += _run_all([[hipcc(), *ARCH, "-shared", "-fPIC", "-o", tmp, *objs]])
+        text += _run_all([[hipcc(), *ARCH, "-shared", "-fPIC", "-o", tmp, *objs, *LIBS]])
         if verbose:
             print(text)
         os.replace(tmp, LIB)

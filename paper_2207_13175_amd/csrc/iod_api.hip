@@ -14,12 +14,34 @@
 #include <numeric>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/iod.h"
 #include "iod_launch.h"
 
 using namespace iodk;
 
 namespace {
+
+// A named range around a host-side phase, for tools that record markers
+// (rocprofv3 --marker-trace); a no-op call when none is attached. Phases that
+// enqueue device work end after synchronising their stream, so the range
+// covers the device time.
+class Phase {
+public:
+    explicit Phase(const char *name) { roctxRangePush(name); }
+    void end()
+    {
+        if (open_) roctxRangePop();
+        open_ = false;
+    }
+    ~Phase() { end(); }
+    Phase(const Phase &) = delete;
+    Phase &operator=(const Phase &) = delete;
+
+private:
+    bool open_ = true;
+};
 
 thread_local char g_err[512];
 
@@ -645,6 +667,7 @@ int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
     if (rc != IOD_OK) return rc;
     if (m < 1 || m > MAX_M) return fail(IOD_EINVAL, "m out of range");
     if (n_iter < 0) return fail(IOD_EINVAL, "n_iter < 0");
+    Phase phase("iod_solve");
     const int64_t ld = round64(m);
     const int64_t wl = iod_swarm_work_len(m);
     const size_t total = (size_t)(20 * ld + wl + (n_iter + 1));
@@ -896,6 +919,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     BatchLayout L;
     int rc = batch_layout(b, params, m, bs, cfg.order, L);
     if (rc != IOD_OK) return rc;
+    Phase swarm_phase(top_k ? "iod_batch: mixed-precision swarm" : "iod_batch: FP64 swarm");
     const int64_t P = b->P, ld = L.ld;
     const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1) + P);
     Stream st;
@@ -970,7 +994,12 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
         hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
         if (e != hipSuccess) rc = hip_fail(e, "final launch");
     }
-    if (rc == IOD_OK && stage) rc = polish_stage_run(b, L, B, *stage, st.s);
+    if (rc == IOD_OK && stage) {
+        HIP_TRY(hipStreamSynchronize(st.s));
+        swarm_phase.end();
+        Phase refine_phase("iod_batch: refinement");
+        rc = polish_stage_run(b, L, B, *stage, st.s);
+    }
     if (rc == IOD_OK && (best_states || best_costs)) {
         std::vector<double> recs((size_t)P * REC);
         hipError_t e = hipMemcpyAsync(recs.data(), B.recs + (n_iter & 1) * P * REC, recs.size() * sizeof(double),
@@ -1148,6 +1177,7 @@ int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t
     if (rc != IOD_OK) return rc;
     if (trial_iters < 2) return fail(IOD_EINVAL, "trial_iters must be >= 2");
     if (top_k < 0 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [0, %d]", TOPK_MAX);
+    Phase phase("iod_batch_autotune");
     const int blocks[3] = {64, 128, 256};
     iod_launch_config best{256, IOD_ORDER_LONGEST_FIRST, 1, 0};
     double best_ms = INFINITY;

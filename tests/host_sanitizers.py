@@ -41,7 +41,7 @@ def build_libiod(out_path: str) -> str:
                             os.path.join(B.CSRC, f)], check=True, capture_output=True)
             objs.append(o)
         subprocess.run([B.hipcc(), *B.ARCH, "-shared", "-fPIC", *HIP_SAN, "-shared-libsan",
-                        "-o", out_path, *objs], check=True, capture_output=True)
+                        "-o", out_path, *objs, *B.LIBS], check=True, capture_output=True)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     return out_path
