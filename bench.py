@@ -281,7 +281,8 @@ def run_refine(args, iod, torch):
                    "steps_range": [int(steps.min()), int(steps.max())],
                    "particle_steps_per_solve": ps,
                    "particle_steps_per_s": ps / elapsed,
-                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph},
+                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
+                                 "waves": cfg.waves},
                    "pos_err_q10_50_90": q(err),
                    "fp64_swarm": {"problem_solves_per_s": wl.P / t64,
                                   "pos_err_q10_50_90": q(e64)},
@@ -325,7 +326,8 @@ def run_batch(args, iod, torch, top_k=0):
                              problem=p, flags=vk["flags"], tol=vk["tol"], tol_lag=vk["tol_lag"])
               for p in range(wl.P)]
     cfg, cand_ms = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
-    print(f"# autotuned: block {cfg.block} order {cfg.order} graph {cfg.graph}", file=sys.stderr,
+    print(f"# autotuned: block {cfg.block} order {cfg.order} graph {cfg.graph} waves {cfg.waves}",
+          file=sys.stderr,
           flush=True)
     steps = iod.iod_batch_steps(b)
 
@@ -390,7 +392,8 @@ def run_batch(args, iod, torch, top_k=0):
                    "particle_steps_per_solve": ps_per_solve,
                    "batch_solves_per_s": args.steps / elapsed,
                    "problem_solves_per_s": args.steps * wl.P / elapsed,
-                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph},
+                   "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
+                                 "waves": cfg.waves},
                    "autotune_ms_per_iter": [round(float(v), 3) for v in cand_ms],
                    "median_pos_err_lu": float(np.median(err)),
                    "finite_costs": int(np.sum(np.isfinite(J)))},

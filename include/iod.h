@@ -109,7 +109,9 @@ typedef struct {
     int32_t order;     /* batches: IOD_ORDER_LONGEST_FIRST (default) or IOD_ORDER_PROBLEM */
     int32_t graph;     /* iod_solve / iod_batch_solve: 1 = replay the iteration launches
                           from one captured hipGraph, 0 = launch them directly */
-    int32_t reserved;  /* must be 0 */
+    int32_t waves;     /* FP64 swarm iteration kernel: 0 = the compiler's register allocation,
+                          3 = registers capped so that at least 3 waves fit per SIMD (an
+                          occupancy choice for iod_batch_autotune); other values are rejected */
 } iod_launch_config;
 
 #define IOD_ORDER_LONGEST_FIRST 0 /* workgroups of problems with more RK4 steps dispatch first */
@@ -408,11 +410,13 @@ int iod_batch_solve_mixed(iod_batch *b, const iod_pso_params *params, const int6
 
 /* Time trial_iters iterations of the batch under each candidate launch
  * configuration (workgroup size 64/128/256 x longest-first/problem order x
- * graph on/off), for the FP64 solve (top_k = 0) or the mixed-precision solve
- * with that top_k, keep the fastest as the batch's configuration and return
- * it in *chosen. If ms_per_iter is given it receives the mean time per
- * iteration of each candidate, in the order block-major, then order, then
- * graph (12 values); *n_candidates receives the count. Synchronous.
+ * graph on/off, and for the FP64 solve also waves 0/3), for the FP64 solve
+ * (top_k = 0) or the mixed-precision solve with that top_k, keep the fastest
+ * as the batch's configuration and return it in *chosen. If ms_per_iter is
+ * given it receives the mean time per iteration of each candidate, in the
+ * order waves-major, then block, then order, then graph (24 values for the
+ * FP64 solve, 12 for the mixed one: ms_per_iter must hold 24);
+ * *n_candidates receives the count. Synchronous.
  * Errors: as iod_batch_solve. */
 int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t *m,
                        int64_t trial_iters, int32_t top_k, iod_launch_config *chosen,

@@ -64,7 +64,7 @@ class iod_swarm(C.Structure):
 
 class iod_launch_config(C.Structure):
     _fields_ = [("block", C.c_int32), ("order", C.c_int32), ("graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("waves", C.c_int32)]
 
 
 IOD_ORDER_LONGEST_FIRST = 0
@@ -351,8 +351,8 @@ def iod_solve(handle: Handle, params: iod_pso_params, m, n_iter):
     return st, J.value, hist
 
 
-def iod_set_config(handle: Handle, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=0):
-    _check(lib().iod_set_config(handle.ptr, C.byref(iod_launch_config(block, order, graph, 0))))
+def iod_set_config(handle: Handle, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=0, waves=0):
+    _check(lib().iod_set_config(handle.ptr, C.byref(iod_launch_config(block, order, graph, waves))))
 
 
 def iod_get_config(handle: Handle) -> iod_launch_config:
@@ -426,8 +426,9 @@ def iod_batch_steps(batch: Batch):
                     dtype=np.int64)
 
 
-def iod_batch_set_config(batch: Batch, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=1):
-    _check(lib().iod_batch_set_config(batch.ptr, C.byref(iod_launch_config(block, order, graph, 0))))
+def iod_batch_set_config(batch: Batch, block=0, order=IOD_ORDER_LONGEST_FIRST, graph=1, waves=0):
+    _check(lib().iod_batch_set_config(batch.ptr, C.byref(iod_launch_config(block, order, graph,
+                                                                            waves))))
 
 
 def iod_batch_get_config(batch: Batch) -> iod_launch_config:
@@ -485,11 +486,12 @@ def iod_batch_solve(batch: Batch, params, m, n_iter, history=True):
 
 
 def iod_batch_autotune(batch: Batch, params, m, trial_iters=4, top_k=0):
-    """(chosen iod_launch_config, ms per iteration of the 12 candidates);
-    top_k = 0 tunes the FP64 solve, top_k > 0 the mixed-precision one."""
+    """(chosen iod_launch_config, ms per iteration of each candidate: 24 for
+    the FP64 solve (top_k = 0, waves 0 and 3), 12 for the mixed-precision one
+    (top_k > 0))."""
     m = np.ascontiguousarray(m, dtype=np.int64)
     cfg = iod_launch_config()
-    ms = np.empty(12)
+    ms = np.empty(24)
     n = C.c_int32()
     _check(lib().iod_batch_autotune(batch.ptr, _params_array(params), m.ctypes.data_as(_I64),
                                     int(trial_iters), int(top_k), C.byref(cfg), _dp(ms),

@@ -99,7 +99,7 @@ int check_config(const iod_launch_config *c)
     if (c->order != IOD_ORDER_LONGEST_FIRST && c->order != IOD_ORDER_PROBLEM)
         return fail(IOD_EINVAL, "unknown order %d", c->order);
     if (c->graph != 0 && c->graph != 1) return fail(IOD_EINVAL, "graph must be 0 or 1");
-    if (c->reserved != 0) return fail(IOD_EINVAL, "reserved must be 0");
+    if (c->waves != 0 && c->waves != 3) return fail(IOD_EINVAL, "waves must be 0 or 3");
     return IOD_OK;
 }
 
@@ -633,7 +633,8 @@ int iod_step(iod_handle *h, iod_swarm *s, const iod_pso_params *p, int64_t n_ite
     SwarmArrays B;
     single_view(h, s, p, D, B);
     for (int64_t j = 1; j <= n_iter; ++j) {
-        HIP_TRY(launch_swarm_iter(D, B, s->block, D.nslots, s->iter + 1, (hipStream_t)stream));
+        HIP_TRY(launch_swarm_iter(D, B, s->block, D.nslots, s->iter + 1, (hipStream_t)stream,
+                                  h->cfg.waves));
         s->iter += 1;
     }
     return IOD_OK;
@@ -695,7 +696,7 @@ int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
         SwarmArrays B;
         single_view(h, &s, p, D, B);
         rc = run_iterations(st.s, h->cfg.graph != 0, 0, n_iter, [&](int64_t n) {
-            return launch_swarm_iter(D, B, s.block, D.nslots, n, st.s);
+            return launch_swarm_iter(D, B, s.block, D.nslots, n, st.s, h->cfg.waves);
         });
         if (rc == IOD_OK) s.iter = n_iter;
     }
@@ -959,7 +960,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     const ProbDesc &d0 = L.descs[0];
     // one iteration: FP64 fused launch, or FP32 launch + top-k + FP64 re-evaluation
     auto iterate = [&](int64_t n) -> hipError_t {
-        if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st.s);
+        if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st.s, cfg.waves);
         hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, st.s);
         if (e == hipSuccess) e = launch_topk(B, B.jp, top_k, cand, st.s);
         if (e == hipSuccess) e = launch_reeval64(B, cand, top_k, n, st.s);
@@ -1179,23 +1180,28 @@ int iod_batch_autotune(iod_batch *b, const iod_pso_params *params, const int64_t
     if (top_k < 0 || top_k > TOPK_MAX) return fail(IOD_EINVAL, "top_k must lie in [0, %d]", TOPK_MAX);
     Phase phase("iod_batch_autotune");
     const int blocks[3] = {64, 128, 256};
+    // the occupancy choice applies to the FP64 iteration kernel only
+    const int n_waves = top_k == 0 ? 2 : 1;
+    const int waves_of[2] = {0, 3};
     iod_launch_config best{256, IOD_ORDER_LONGEST_FIRST, 1, 0};
     double best_ms = INFINITY;
     int32_t c = 0;
-    for (int bi = 0; bi < 3; ++bi)
-        for (int order = 0; order < 2; ++order)
-            for (int graph = 0; graph < 2; ++graph) {
-                iod_launch_config cfg{blocks[bi], order, graph, 0};
-                double ms = 0;
-                rc = batch_run(b, params, m, trial_iters, cfg, nullptr, nullptr, nullptr, &ms, top_k);
-                if (rc != IOD_OK) return rc;
-                if (ms_per_iter) ms_per_iter[c] = ms;
-                ++c;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = cfg;
+    for (int wi = 0; wi < n_waves; ++wi)
+        for (int bi = 0; bi < 3; ++bi)
+            for (int order = 0; order < 2; ++order)
+                for (int graph = 0; graph < 2; ++graph) {
+                    iod_launch_config cfg{blocks[bi], order, graph, waves_of[wi]};
+                    double ms = 0;
+                    rc = batch_run(b, params, m, trial_iters, cfg, nullptr, nullptr, nullptr, &ms,
+                                   top_k);
+                    if (rc != IOD_OK) return rc;
+                    if (ms_per_iter) ms_per_iter[c] = ms;
+                    ++c;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = cfg;
+                    }
                 }
-            }
     if (n_candidates) *n_candidates = c;
     b->cfg = best;
     if (chosen) *chosen = best;

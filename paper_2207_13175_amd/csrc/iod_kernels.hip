@@ -249,9 +249,9 @@ __global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
     if (tile == 0 && threadIdx.x == 0) B.stop[p] = -1.0;
 }
 
-// Algorithm 1, iteration n >= 1.
+// Algorithm 1, iteration n >= 1 (the body of the iteration kernels below).
 template <int BS, bool SINGLE>
-__global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, int64_t n)
+__device__ __forceinline__ void swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int64_t n)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
@@ -326,6 +326,22 @@ __global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, i
 
     // (c) this workgroup's best personal best, for the next launch
     write_slot(jp, i, valid, Pb, slot_cur, red, wst);
+}
+
+// The iteration kernel with the compiler's register allocation ...
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) void k_swarm_iter(ProbDesc d0, SwarmArrays B, int64_t n)
+{
+    swarm_iter<BS, SINGLE>(d0, B, n);
+}
+
+// ... and with registers capped so that at least three waves fit per SIMD
+// (a launch-configuration choice: same arithmetic, same results).
+template <int BS, bool SINGLE>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_swarm_iter_w3(
+    ProbDesc d0, SwarmArrays B, int64_t n)
+{
+    swarm_iter<BS, SINGLE>(d0, B, n);
 }
 
 // Global best after iteration n, one workgroup per problem:
@@ -427,11 +443,17 @@ hipError_t launch_swarm_init(const ProbDesc &d0, const SwarmArrays &B, int bs, i
 }
 
 hipError_t launch_swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             int64_t n, hipStream_t st)
+                             int64_t n, hipStream_t st, int waves)
 {
     const bool single = B.desc == nullptr;
-    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_swarm_iter<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n);
-                        else hipLaunchKernelGGL((k_swarm_iter<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    if (waves != 0 && waves != 3) return hipErrorInvalidValue;
+    if (waves == 3) {
+        IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_swarm_iter_w3<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n);
+                            else hipLaunchKernelGGL((k_swarm_iter_w3<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    } else {
+        IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_swarm_iter<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n);
+                            else hipLaunchKernelGGL((k_swarm_iter<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    }
     return hipGetLastError();
 }
 

@@ -26,8 +26,10 @@ hipError_t launch_eval(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t
                        hipStream_t st);
 hipError_t launch_swarm_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                              hipStream_t st);
+// waves: 0 = the compiler's register allocation, 3 = registers capped so
+// that at least three waves fit per SIMD (same results).
 hipError_t launch_swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             int64_t n, hipStream_t st);
+                             int64_t n, hipStream_t st, int waves = 0);
 hipError_t launch_swarm_final(const ProbDesc &d0, const SwarmArrays &B, int64_t n, hipStream_t st);
 
 // Mixed precision (FP32 ranking, FP64 global best); batched launches only.

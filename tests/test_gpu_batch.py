@@ -75,15 +75,16 @@ def test_batch_all_launch_configs_bitwise(torch_dev):
     _, obs = observe(wl)
     b = make_batch(wl, obs)
     ref = None
-    for block in (64, 128, 256):
-        for order in (iod.IOD_ORDER_LONGEST_FIRST, iod.IOD_ORDER_PROBLEM):
-            for graph in (0, 1):
-                iod.iod_batch_set_config(b, block=block, order=order, graph=graph)
-                out = iod.iod_batch_solve(b, params_of(wl), wl.m, wl.n_iter)
-                if ref is None:
-                    ref = out
-                for a, r in zip(out, ref):
-                    assert np.array_equal(a, r), (block, order, graph)
+    for waves in (0, 3):
+        for block in (64, 128, 256):
+            for order in (iod.IOD_ORDER_LONGEST_FIRST, iod.IOD_ORDER_PROBLEM):
+                for graph in (0, 1):
+                    iod.iod_batch_set_config(b, block=block, order=order, graph=graph, waves=waves)
+                    out = iod.iod_batch_solve(b, params_of(wl), wl.m, wl.n_iter)
+                    if ref is None:
+                        ref = out
+                    for a, r in zip(out, ref):
+                        assert np.array_equal(a, r), (waves, block, order, graph)
 
 
 def test_batch_eval_parity_ragged(torch_dev):
@@ -119,11 +120,15 @@ def test_batch_autotune_picks_a_config(torch_dev):
     _, obs = observe(wl)
     b = make_batch(wl, obs)
     cfg, ms = iod.iod_batch_autotune(b, params_of(wl), wl.m, trial_iters=3)
-    assert len(ms) == 12 and np.all(ms > 0)
-    assert cfg.block in (64, 128, 256)
+    assert len(ms) == 24 and np.all(ms > 0)
+    assert cfg.block in (64, 128, 256) and cfg.waves in (0, 3)
     got = iod.iod_batch_get_config(b)
-    assert (got.block, got.order, got.graph) == (cfg.block, cfg.order, cfg.graph)
-    assert ms.min() == ms[[64, 128, 256].index(cfg.block) * 4 + cfg.order * 2 + cfg.graph]
+    assert (got.block, got.order, got.graph, got.waves) == (cfg.block, cfg.order, cfg.graph, cfg.waves)
+    assert ms.min() == ms[(cfg.waves // 3) * 12 + [64, 128, 256].index(cfg.block) * 4
+                          + cfg.order * 2 + cfg.graph]
+    # the mixed-precision tuning has no occupancy choice: 12 candidates
+    cfg32, ms32 = iod.iod_batch_autotune(b, params_of(wl), wl.m, trial_iters=3, top_k=16)
+    assert len(ms32) == 12 and cfg32.waves == 0
 
 
 @pytest.mark.parametrize("block", [64, 128, 256])
@@ -141,6 +146,10 @@ def test_single_solve_graph_and_block_sizes_bitwise(torch_dev, block):
         out = iod.iod_solve(h, p, 300, 12)
         for a, r in zip(out, ref):
             assert np.array_equal(a, r)
+    iod.iod_set_config(h, block=block, graph=1, waves=3)
+    out = iod.iod_solve(h, p, 300, 12)
+    for a, r in zip(out, ref):
+        assert np.array_equal(a, r)
 
 
 def observe_single(wl):
@@ -168,3 +177,15 @@ def test_batch_full_size_sampled(torch_dev):
             assert abs(J[p] - want) <= COST_RTOL * abs(want), p
         else:
             assert not np.isfinite(J[p])
+
+
+def test_launch_config_rejects_unknown_values(torch_dev):
+    wl = W.c0(0)
+    _, obs = observe_single(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    for kw in ({"waves": 2}, {"waves": -1}, {"block": 96}, {"graph": 2}, {"order": 5}):
+        with pytest.raises(iod.IodError):
+            iod.iod_set_config(h, **kw)
+    iod.iod_set_config(h, block=64, waves=3)
+    got = iod.iod_get_config(h)
+    assert (got.block, got.waves) == (64, 3)
