@@ -1276,7 +1276,8 @@ constexpr double GEO_ALPHA = 0.75;  // accept the correction a if 2 |a| <= alpha
 int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
                       const int32_t *n, int64_t P, int32_t T, int32_t n_iter, double *chi2,
                       double *work, double *vt, double *jrows, int32_t n_cand, int32_t *active,
-                      int32_t *done, int64_t ld, hipStream_t st)
+                      int32_t *done, const int32_t *lanes, int64_t nlanes, int64_t ld,
+                      hipStream_t st)
 {
     const int64_t jld = P * n_cand;
     double *jtj = work;
@@ -1294,11 +1295,17 @@ int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
     TB.desc = tdesc;
     TB.x = xt;
     TB.cost = chi2t;
+    // the normal equations and the gradient see only the candidates: packed,
+    // several problems' candidates to a wave
+    Lanes KL;
+    KL.pairs = lanes;
+    KL.n = nlanes;
+    const int64_t kgrid = (nlanes + 63) / 64;
     for (int32_t it = 0; it < n_iter; ++it) {
-        HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st, jrows, n_cand, jld));
+        HIP_TRY(launch_normal(d0, PB, 64, kgrid, chi2, jtj, jtr, st, jrows, n_cand, jld, KL));
         SwarmArrays GB = PB;
         GB.cost = cost;
-        HIP_TRY(launch_grad(d0, GB, 64, P, g, adj, ld, 1, st));
+        HIP_TRY(launch_grad(d0, GB, 64, kgrid, g, adj, ld, 1, st, KL));
         HIP_TRY(launch_gn_trials(x, jtj, g, lam, n, active, done, T, P, ld, xt, vt, st));
         HIP_TRY(launch_geo(PB.desc, x, jtj, jtr, jrows, n_cand, jld, lam, n, active, done, T, P,
                            ld, GEO_HD, GEO_ALPHA, vt, xt, st));
@@ -1319,7 +1326,7 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     // trials per candidate: the free lanes of the problem's 64-lane wave, at most 8
     const int32_t T = std::max(1, std::min(8, 64 / S.n_cand));
     DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc, dtdesc, dact,
-        ddone, dvt, djrows;
+        ddone, dvt, djrows, dlanes;
     // rows of J of every candidate: max over problems of K R (R = 3 with ranges, else 2)
     int64_t jrow_max = 0;
     for (const HostProblem &Pb : b->probs)
@@ -1371,6 +1378,22 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     HIP_TRY(hipMemcpyAsync(dlist.p, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dn.p, n.data(), n.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dtdesc.p, td.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    // packed lanes: (problem, candidate), problems with the most RK4 steps first
+    std::vector<int32_t> by_steps(P);
+    std::iota(by_steps.begin(), by_steps.end(), 0);
+    std::stable_sort(by_steps.begin(), by_steps.end(), [&](int32_t a, int32_t c) {
+        return b->probs[a].steps > b->probs[c].steps;
+    });
+    std::vector<int32_t> lanes;
+    lanes.reserve((size_t)2 * P * S.n_cand);
+    for (int32_t p : by_steps)
+        for (int32_t j = 0; j < n[p]; ++j) {
+            lanes.push_back(p);
+            lanes.push_back(j);
+        }
+    const int64_t nlanes = (int64_t)lanes.size() / 2;
+    HIP_TRY(hipMalloc(&dlanes.p, lanes.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(dlanes.p, lanes.data(), lanes.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dact.p, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ddone.p, dn0.data(), dn0.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     SwarmArrays PB;
@@ -1383,7 +1406,7 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
     int rc = polish_trials_run(pd[0], PB, (const ProbDesc *)dtdesc.p, (const int32_t *)dn.p, P, T,
                                S.n_gn, (double *)dchi.p, (double *)dwork.p, (double *)dvt.p,
                                (double *)djrows.p, S.n_cand, (int32_t *)dact.p,
-                               (int32_t *)ddone.p, ldp, st);
+                               (int32_t *)ddone.p, (const int32_t *)dlanes.p, nlanes, ldp, st);
     if (rc != IOD_OK) return rc;
     HIP_TRY(launch_pick_best((const double *)dx.p, (const double *)dchi.p, (const int32_t *)dn.p, P,
                              ldp, stride, (double *)dbest.p, (double *)dbchi.p, st));

@@ -77,6 +77,13 @@ struct SwarmArrays {
                                       // gradient or normal-equation launch exit at once; null: all run
 };
 
+// Packed placement of the gradient and normal-equation launches: one
+// (problem, particle) pair per thread, [n][2]; null: one problem per workgroup.
+struct Lanes {
+    const int32_t *pairs = nullptr;
+    int64_t n = 0;
+};
+
 // Largest top-k of the mixed-precision ranking.
 constexpr int TOPK_MAX = 256;
 

@@ -222,16 +222,17 @@ constexpr int CKPT = 64;   // steps between adjoint checkpoints
 // observation's cotangent at its grid index. Scratch per lane (column g of
 // a [rows][6][wld] array): rows [0, nseg) checkpoints, [nseg, nseg + 64)
 // segment states. mode >= 0 overrides the cost mode.
-template <int BS, bool SINGLE>
-__global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double *__restrict__ grad,
-                                             double *__restrict__ work, int64_t wld, int32_t mode)
+template <int BS, int PLACE>
+__global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L,
+                                             double *__restrict__ grad, double *__restrict__ work,
+                                             int64_t wld, int32_t mode)
 {
-    int64_t p, tile;
-    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
-    if (B.active && !B.active[p]) return;   // whole workgroup
+    int64_t p, i;
+    const ProbDesc *Dp;
+    if (!place<BS, PLACE>(d0, B, L, p, i, Dp)) return;
+    const ProbDesc &D = *Dp;
     KArgs A = D.k;
     if (mode >= 0) A.mode = mode;
-    const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     const int64_t g = D.off + (valid ? i : D.m - 1);
     const int32_t S = A.ns[A.K - 1];
@@ -244,13 +245,14 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
     load_state(B.x, B.ld, g, X);
     double J = 0.0;
     CostAcc acc{0.0, A.w, A.mode, A.wr};
-    int32_t k = 0;
+    // k: next observation, nk: the step it is taken after (-1 past the last)
+    int32_t k = 0, nk = A.ns[0];
     for (int32_t n = 0; n <= S; ++n) {
         if (n < S && n % CKPT == 0 && valid) {
 #pragma unroll
             for (int d = 0; d < 6; ++d) ck[((int64_t)(n / CKPT) * 6 + d) * wld + g] = X[d];
         }
-        while (k < A.K && A.ns[k] == n) {
+        while (nk == n) {
             const double *row = A.tab + (int64_t)k * TAB_W;
             double Sx[6];
 #pragma unroll
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
             if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sx);
             acc(row, Sx);
             ++k;
+            nk = k < A.K ? A.ns[k] : -1;
         }
         if (n < S) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
     }
@@ -266,12 +269,14 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
     // reverse sweep
     double lam[6] = {0, 0, 0, 0, 0, 0};
     k = A.K - 1;
-    while (k >= 0 && A.ns[k] == S) {
+    nk = A.ns[k];
+    while (nk == S) {
         double add[6];
         obs_cotangent(A, A.tab + (int64_t)k * TAB_W, X, add);
 #pragma unroll
         for (int d = 0; d < 6; ++d) lam[d] += add[d];
         --k;
+        nk = k >= 0 ? A.ns[k] : -1;
     }
     for (int32_t sg = nseg - 1; sg >= 0; --sg) {
         const int32_t a = sg * CKPT, b = min(a + CKPT, S);
@@ -290,12 +295,13 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, double 
 #pragma unroll
             for (int d = 0; d < 6; ++d) Xj[d] = valid ? seg[((int64_t)(j - a) * 6 + d) * wld + g] : X[d];
             rk4_vjp(A.mu, A.mu1, A.h, Xj, lam);
-            while (k >= 0 && A.ns[k] == j) {
+            while (nk == j) {
                 double add[6];
                 obs_cotangent(A, A.tab + (int64_t)k * TAB_W, Xj, add);
 #pragma unroll
                 for (int d = 0; d < 6; ++d) lam[d] += add[d];
                 --k;
+                nk = k >= 0 ? A.ns[k] : -1;
             }
         }
     }
@@ -349,17 +355,17 @@ __device__ __forceinline__ void tangent_step(double mu, double mu1, double h, do
     for (int d = 0; d < 6; ++d) X[d] = Y[d];
 }
 
-template <int BS, bool SINGLE>
-__global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, double *__restrict__ chi2,
-                                               double *__restrict__ jtj, double *__restrict__ jtr,
-                                               double *__restrict__ jrows, int64_t jstride,
-                                               int64_t jld)
+template <int BS, int PLACE>
+__global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes L,
+                                               double *__restrict__ chi2, double *__restrict__ jtj,
+                                               double *__restrict__ jtr, double *__restrict__ jrows,
+                                               int64_t jstride, int64_t jld)
 {
-    int64_t p, tile;
-    const ProbDesc &D = locate<SINGLE>(d0, B, p, tile);
-    if (B.active && !B.active[p]) return;   // whole workgroup
+    int64_t p, i;
+    const ProbDesc *Dp;
+    if (!place<BS, PLACE>(d0, B, L, p, i, Dp)) return;
+    const ProbDesc &D = *Dp;
     const KArgs &A = D.k;
-    const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     const int64_t g = D.off + (valid ? i : D.m - 1);
     const double is = sqrt(A.w);   // 1 / sigma
@@ -375,9 +381,10 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
 #pragma unroll
     for (int d = 0; d < 6; ++d) gr[d] = 0.0;
     const int32_t S = A.ns[A.K - 1];
-    int32_t k = 0;
+    // k: next observation, nk: the step it is taken after (-1 past the last)
+    int32_t k = 0, nk = A.ns[0];
     for (int32_t n = 0; n <= S; ++n) {
-        while (k < A.K && A.ns[k] == n) {
+        while (nk == n) {
             const double *row = A.tab + (int64_t)k * TAB_W;
             double Sx[6], SP[36];
 #pragma unroll
@@ -429,6 +436,7 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, doubl
                 }
             }
             ++k;
+            nk = k < A.K ? A.ns[k] : -1;
         }
         if (n < S) tangent_step(A.mu, A.mu1, A.h, X, Phi);
     }
@@ -771,21 +779,32 @@ __global__ __launch_bounds__(BS) void k_gn_accept(ProbDesc d0, SwarmArrays B,
 // ---------------------------------------------------------------------------
 
 hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st)
+                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st,
+                       const Lanes &L)
 {
-    const bool single = B.desc == nullptr;
-    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_grad<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, grad, work, wld, mode);
-                        else hipLaunchKernelGGL((k_grad<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, grad, work, wld, mode));
+    if (L.pairs) {
+        if (bs != 64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_grad<64, PLACE_PACKED>), dim3((unsigned)grid), dim3(64), 0, st, d0, B, L, grad, work, wld, mode);
+    } else if (B.desc == nullptr) {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_grad<BS_, PLACE_SINGLE>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, grad, work, wld, mode));
+    } else {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_grad<BS_, PLACE_BATCH>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, grad, work, wld, mode));
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                          double *chi2, double *jtj, double *jtr, hipStream_t st, double *jrows,
-                         int64_t jstride, int64_t jld)
+                         int64_t jstride, int64_t jld, const Lanes &L)
 {
-    const bool single = B.desc == nullptr;
-    IOD_DISPATCH_BS(bs, if (single) hipLaunchKernelGGL((k_normal<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr, jrows, jstride, jld);
-                        else hipLaunchKernelGGL((k_normal<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, chi2, jtj, jtr, jrows, jstride, jld));
+    if (L.pairs) {
+        if (bs != 64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_normal<64, PLACE_PACKED>), dim3((unsigned)grid), dim3(64), 0, st, d0, B, L, chi2, jtj, jtr, jrows, jstride, jld);
+    } else if (B.desc == nullptr) {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_normal<BS_, PLACE_SINGLE>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, chi2, jtj, jtr, jrows, jstride, jld));
+    } else {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_normal<BS_, PLACE_BATCH>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, chi2, jtj, jtr, jrows, jstride, jld));
+    }
     return hipGetLastError();
 }
 
