@@ -1263,11 +1263,13 @@ int polish_run(const ProbDesc &d0, SwarmArrays B, int bs, int64_t grid, int32_t 
 }
 
 // The batched refinement loop: each iteration forms the normal equations and
-// the adjoint gradient of every live candidate, tries T dampings per
-// candidate side by side (the lanes of the problem's wave that the
-// candidates leave free), keeps the best trial, and retires problems whose
-// candidates have all stopped moving. PB holds the candidate columns
-// (p * 64 + j, j < n[p]); tdesc the trial descriptors (n[p] * T columns).
+// the adjoint gradient of every live candidate (packed: lanes lists the
+// (problem, candidate) pairs, several problems to a wave), tries T dampings
+// per candidate side by side (one wave per problem, in the lanes that the
+// candidates leave free), adds the geodesic correction, keeps the best
+// trial, and retires problems whose candidates have all stopped moving. PB
+// holds the candidate columns (p * 64 + j, j < n[p]); tdesc the trial
+// descriptors (n[p] * T columns); jrows the candidates' rows of J.
 constexpr double POLISH_STEP_TOL = 1e-12;
 
 constexpr double GEO_HD = 0.1;      // finite-difference step along v, as a fraction of v
