@@ -33,13 +33,18 @@ def build_libiod(out_path: str) -> str:
     from paper_2207_13175_amd import build as B
     tmp = tempfile.mkdtemp(prefix="iod_san_")
     try:
-        objs = []
+        objs, procs = [], []
+        flags = [x for x in B.FLAGS if x != "-O3"] + ["-O1", "-g"]
         for f, _ in B.UNITS:
             o = os.path.join(tmp, f.replace(".hip", ".o"))
-            flags = [x for x in B.FLAGS if x != "-O3"] + ["-O1", "-g"]
-            subprocess.run([B.hipcc(), *B.ARCH, *flags, *HIP_SAN, "-c", "-o", o,
-                            os.path.join(B.CSRC, f)], check=True, capture_output=True)
+            procs.append(subprocess.Popen([B.hipcc(), *B.ARCH, *flags, *HIP_SAN, "-c", "-o", o,
+                                           os.path.join(B.CSRC, f)],
+                                          stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
             objs.append(o)
+        for pr in procs:
+            out = pr.communicate()[0]
+            if pr.returncode != 0:
+                raise RuntimeError(out.decode(errors="replace"))
         subprocess.run([B.hipcc(), *B.ARCH, "-shared", "-fPIC", *HIP_SAN, "-shared-libsan",
                         "-o", out_path, *objs, *B.LIBS], check=True, capture_output=True)
     finally:
