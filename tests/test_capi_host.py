@@ -153,3 +153,50 @@ def test_build_compiles_every_kernel_source():
     assert dict(B.UNITS)["iod_mixed.hip"] == []
     assert "-ffp-contract=off" in B.FLAGS
     assert "-packed-fp32-ops" in B.FLAGS
+
+
+def test_library_and_oracle_share_nothing():
+    """The GPU library and the oracle are separate: no source of the package
+    (Python, HIP, headers) imports, includes or loads the oracle, and the
+    oracle imports nothing of the package. The benchmark touches the oracle
+    only inside its CPU-baseline leg."""
+    import ast
+    import glob
+    pkg = os.path.join(ROOT, "paper_2207_13175_amd")
+    for f in glob.glob(os.path.join(pkg, "*.py")):
+        for node in ast.walk(ast.parse(open(f).read())):
+            if isinstance(node, (ast.Import, ast.ImportFrom)):
+                names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
+                assert not any(n.split(".")[0] == "oracle" for n in names), f
+    for f in glob.glob(os.path.join(pkg, "csrc", "*")) + [os.path.join(ROOT, "include", "iod.h")]:
+        src = open(f).read()
+        assert not re.search(r'#include\s*[<"][^>"]*(orc|oracle)', src), f
+        assert "liborc" not in src and "orc_" not in src, f
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*")):
+        if f.endswith((".py", ".c", ".h")):
+            src = open(f).read()
+            assert "paper_2207_13175_amd" not in src and "libiod" not in src and "iod.h" not in src, f
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = [fn.name for fn in tree.body if isinstance(fn, ast.FunctionDef)
+             and any(isinstance(n, ast.Import) and any(a.name == "oracle" for a in n.names)
+                     for n in ast.walk(fn))]
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
+           and any(a.name.split(".")[0] == "oracle" for a in n.names)]
+    assert users == ["cpu_baseline"] and not top
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libiod.so the binding raises on first use; there is no other
+    code path to fall back to."""
+    import subprocess
+    import sys
+    code = ("import paper_2207_13175_amd as iod\n"
+            f"iod.LIB_PATH = {str(tmp_path / 'libiod.so')!r}\n"
+            "try:\n"
+            "    iod.iod_version()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("raised") and "is not built" in r.stdout, r.stdout
