@@ -150,22 +150,42 @@ __device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6]
     for (; n > 0; --n) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
 }
 
+// Who stages the observation table into LDS together: the whole workgroup
+// (with barriers), or one wave on its own. A wave's lanes run in lockstep and
+// its LDS accesses complete in issue order, so a wave needs only a fence
+// that keeps the compiler from moving accesses across the hand-over.
+struct BlockScope {
+    static __device__ __forceinline__ int32_t rank() { return threadIdx.x; }
+    static __device__ __forceinline__ int32_t size() { return blockDim.x; }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveScope {
+    static __device__ __forceinline__ int32_t rank() { return threadIdx.x & 63; }
+    static __device__ __forceinline__ int32_t size() { return 64; }
+    static __device__ __forceinline__ void sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+};
+
 // Walk the observation schedule: advance X on the grid, and at each
 // observation hand the state there (a side copy advanced by the partial step
-// when the time is off the grid) to `obs(row, S)`. Every thread of the
-// workgroup must call this (it stages the table through LDS with barriers).
-template <class Obs>
+// when the time is off the grid) to `obs(row, S)`. Every thread of the scope
+// (the workgroup, or the wave) must call this: it stages the table through
+// LDS in chunks.
+template <class Scope = BlockScope, class Obs>
 __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, int32_t *lds_ns,
                                      Obs &obs)
 {
     int32_t step = 0;
     for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
         const int32_t nk = min(OBS_CHUNK, A.K - k0);
-        __syncthreads();
-        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
+        Scope::sync();
+        for (int32_t j = Scope::rank(); j < nk * TAB_W; j += Scope::size())
             lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
-        for (int32_t j = threadIdx.x; j < nk; j += blockDim.x) lds_ns[j] = A.ns[k0 + j];
-        __syncthreads();
+        for (int32_t j = Scope::rank(); j < nk; j += Scope::size()) lds_ns[j] = A.ns[k0 + j];
+        Scope::sync();
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
             const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
@@ -232,6 +252,7 @@ struct CostAcc {
     }
 };
 
+template <class Scope = BlockScope>
 __device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], double *lds,
                                             int32_t *lds_ns)
 {
@@ -239,7 +260,7 @@ __device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], 
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = x0[d];
     CostAcc acc{0.0, A.w, A.mode, A.wr};
-    walk(A, X, lds, lds_ns, acc);
+    walk<Scope>(A, X, lds, lds_ns, acc);
     return acc.J;
 }
 
@@ -364,8 +385,8 @@ __device__ __forceinline__ bool lex_less(double ka, double ia, double kb, double
     return ka < kb || (ka == kb && ia < ib);
 }
 
-// Block-wide argmin; every thread returns the minimum. red: LDS [2 * waves].
-__device__ __forceinline__ void block_argmin(double &key, double &idx, double *red)
+// Wave-wide argmin by butterfly exchanges; every lane returns the minimum.
+__device__ __forceinline__ void wave_argmin(double &key, double &idx)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -376,6 +397,12 @@ __device__ __forceinline__ void block_argmin(double &key, double &idx, double *r
             idx = oi;
         }
     }
+}
+
+// Block-wide argmin; every thread returns the minimum. red: LDS [2 * waves].
+__device__ __forceinline__ void block_argmin(double &key, double &idx, double *red)
+{
+    wave_argmin(key, idx);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[2 * wave] = key;

@@ -379,35 +379,43 @@ __global__ __launch_bounds__(TOPK_BS) void k_topk(SwarmArrays B, const double *_
     if (t < top_k) out[p * top_k + t] = si[t] < (double)D.m ? (int32_t)si[t] : -1;
 }
 
-// Per problem (one workgroup of 64 threads): FP64 costs of the personal
-// bests of the selected candidates; the lowest (cost, index) replaces the
-// record of iteration n-1 if the record is empty or the cost is strictly
-// lower. Writes record n and hist[n].
-__global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *__restrict__ cand,
-                                                 int32_t top_k, int64_t n)
+// Per problem (one wave; RE_WAVES problems to a workgroup, so they run on
+// the SIMDs of one compute unit instead of sharing one): FP64 costs of the
+// personal bests of the selected candidates; the lowest (cost, index)
+// replaces the record of iteration n-1 if the record is empty or the cost is
+// strictly lower. Writes record n and hist[n]. The waves never wait for each
+// other: each stages its own problem's observation table.
+constexpr int RE_WAVES = 4;
+
+__global__ __launch_bounds__(64 * RE_WAVES) void k_reeval64(SwarmArrays B,
+                                                            const int32_t *__restrict__ cand,
+                                                            int32_t top_k, int64_t n)
 {
-    __shared__ double lds[OBS_CHUNK * TAB_W];
-    __shared__ int32_t lds_ns[OBS_CHUNK];
-    __shared__ double red[2];
-    __shared__ double wst[6];
-    const int64_t p = B.porder ? B.porder[blockIdx.x] : blockIdx.x;
+    __shared__ double lds_w[RE_WAVES][OBS_CHUNK * TAB_W];
+    __shared__ int32_t ns_w[RE_WAVES][OBS_CHUNK];
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t q = (int64_t)blockIdx.x * RE_WAVES + wave;
+    if (q >= B.nprob) return;
+    double *lds = lds_w[wave];
+    int32_t *lds_ns = ns_w[wave];
+    const int64_t p = B.porder ? B.porder[q] : q;
     const ProbDesc &D = B.desc[p];
     const double *prev = B.recs + (((n - 1) & 1) * B.nprob + p) * REC;
     double *cur = B.recs + ((n & 1) * B.nprob + p) * REC;
     if (B.stop[p] >= 0.0) {
         // ended by Algorithm 2: carry the final record forward
-        if (threadIdx.x < REC) cur[threadIdx.x] = prev[threadIdx.x];
-        if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = NAN;
+        if (lane < REC) cur[lane] = prev[lane];
+        if (lane == 0 && D.hist && n < D.hist_len) D.hist[n] = NAN;
         return;
     }
     double bkey = INFINITY, bidx = INFINITY, bst[6] = {0, 0, 0, 0, 0, 0};
     for (int c0 = 0; c0 < top_k; c0 += 64) {
-        const int c = c0 + (int)threadIdx.x;
+        const int c = c0 + lane;
         const int32_t i = c < top_k ? cand[p * top_k + c] : -1;
         const bool valid = i >= 0;
         double X[6];
         load_state(B.p, B.ld, D.off + (valid ? i : 0), X);
-        const double J = eval_cost(D.k, X, lds, lds_ns);
+        const double J = eval_cost<WaveScope>(D.k, X, lds, lds_ns);
         const double k = valid ? cost_key(J) : INFINITY, ix = valid ? (double)i : INFINITY;
         if (lex_less(k, ix, bkey, bidx)) {
             bkey = k;
@@ -417,28 +425,30 @@ __global__ __launch_bounds__(64) void k_reeval64(SwarmArrays B, const int32_t *_
         }
     }
     double key = bkey, idx = bidx;
-    block_argmin(key, idx, red);
-    if (bidx == idx && bkey == key) {
+    wave_argmin(key, idx);
+    // the winner's state from the one lane that holds it (candidate indices
+    // are distinct; with no valid candidate the record is kept)
+    const uint64_t holders = __ballot(bidx == idx && bkey == key);
+    const int src = holders ? __ffsll((unsigned long long)holders) - 1 : 0;
+    double w[6];
 #pragma unroll
-        for (int d = 0; d < 6; ++d) wst[d] = bst[d];
-    }
-    __syncthreads();
+    for (int d = 0; d < 6; ++d) w[d] = __shfl(bst[d], src, 64);
     double g[6], gkey, gidx;
     if (idx < INFINITY && (prev[1] < 0.0 || key < prev[0])) {
         gkey = key;
         gidx = idx;
 #pragma unroll
-        for (int d = 0; d < 6; ++d) g[d] = wst[d];
+        for (int d = 0; d < 6; ++d) g[d] = w[d];
     } else {
         gkey = prev[0];
         gidx = prev[1];
 #pragma unroll
         for (int d = 0; d < 6; ++d) g[d] = prev[2 + d];
     }
-    write_record(cur, g, gkey, gidx);
-    if (threadIdx.x == 0 && D.hist && n < D.hist_len) D.hist[n] = gkey;
+    if (lane < REC) cur[lane] = lane == 0 ? gkey : lane == 1 ? gidx : g[lane - 2];
+    if (lane == 0 && D.hist && n < D.hist_len) D.hist[n] = gkey;
     // Algorithm 2 after iteration n
-    if (threadIdx.x == 0 && D.tol > 0.0 && n > D.tol_lag &&
+    if (lane == 0 && D.tol > 0.0 && n > D.tol_lag &&
         tolerance_met(gkey, D.hist[n - D.tol_lag], D.tol))
         B.stop[p] = (double)n;
 }
@@ -485,7 +495,8 @@ hipError_t launch_topk(const SwarmArrays &B, const double *keys, int32_t top_k, 
 hipError_t launch_reeval64(const SwarmArrays &B, const int32_t *cand, int32_t top_k, int64_t n,
                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reeval64, dim3((unsigned)B.nprob), dim3(64), 0, st, B, cand, top_k, n);
+    hipLaunchKernelGGL(k_reeval64, dim3((unsigned)((B.nprob + RE_WAVES - 1) / RE_WAVES)),
+                       dim3(64 * RE_WAVES), 0, st, B, cand, top_k, n);
     return hipGetLastError();
 }
 
