@@ -135,6 +135,26 @@ def test_topk_selection_exact(torch_dev):
             assert np.array_equal(got[p], want), (top_k, p)
 
 
+def test_reevaluation_picks_the_fp64_argmin_of_the_initial_swarm(torch_dev):
+    """With top_k >= m the FP64 re-evaluation sees every particle. After
+    initialisation (and after iteration 1, which reuses the initial costs)
+    the global best is therefore the FP64 argmin of Algorithm 1's initial
+    swarm, which the oracle computes. The batch has observation tables longer
+    than one staging chunk (K > 64) and a problem count that leaves part of
+    the last re-evaluation workgroup idle."""
+    wl = W.c2(5, P=5, n_iter=1, m_range=(64, 250), K_range=(65, 80), T_range=(0.6, 0.9))
+    assert min(len(t) for t in wl.t) > 64
+    probs, obs = observe(wl)
+    b = iod.iod_create_batch([wl.mu] * wl.P, wl.chief, wl.t, obs, [wl.sigma] * wl.P, h=wl.h)
+    g, J, hist = iod.iod_batch_solve_mixed(b, params_of(wl), wl.m, 1, top_k=256)
+    assert np.array_equal(hist[:, 0], J) and np.array_equal(hist[:, 1], J)
+    for p in range(wl.P):
+        S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+        ref = oracle.pso_init(probs[p], S, int(wl.m[p]))
+        assert abs(J[p] - ref.jg.value) <= COST_RTOL * abs(ref.jg.value), (p, J[p], ref.jg.value)
+        assert np.array_equal(g[p], ref.g), p
+
+
 def test_mixed_solve_reports_fp64_results(torch_dev):
     """Reported global bests carry FP64 costs of their states; histories
     never increase; the mixed pipeline lands in the same basin as the FP64
