@@ -393,7 +393,9 @@ __global__ __launch_bounds__(64 * RE_WAVES) void k_reeval64(SwarmArrays B,
 {
     __shared__ double lds_w[RE_WAVES][OBS_CHUNK * TAB_W];
     __shared__ int32_t ns_w[RE_WAVES][OBS_CHUNK];
-    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    // wave-uniform (readfirstlane), so the problem's descriptor reads are scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = (int)(threadIdx.x & 63);
     const int64_t q = (int64_t)blockIdx.x * RE_WAVES + wave;
     if (q >= B.nprob) return;
     double *lds = lds_w[wave];
