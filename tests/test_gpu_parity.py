@@ -161,6 +161,55 @@ def test_eval_nonfinite_cases(torch_dev):
     assert_cost_parity(got, want)
 
 
+def random_problem(seed):
+    """A seeded random problem well away from the workload recipes: mass
+    ratio anywhere in [0, 0.5], a chief anywhere in the Earth-Moon region,
+    on- and off-grid observation times (sometimes one at the epoch), random
+    observed angles, and particles spread from 1e-4 to 1 LU around the chief
+    (some of them pass close to a primary)."""
+    rng = np.random.default_rng([77, seed])
+    mu = [0.0, 1e-30, 0.012150585, float(rng.uniform(0, 0.5)), 0.5][seed % 5]
+    h = [1e-3, 5e-4, 2e-3, float(rng.uniform(2e-4, 3e-3))][seed % 4]
+    K = int(rng.integers(1, 90))
+    T = float(rng.uniform(0.05, 1.2))
+    grid = np.round(rng.uniform(0, T, K) / h) * h
+    off = rng.uniform(0, T, K)
+    t = np.unique(np.where(rng.random(K) < 0.5, grid, off))
+    if seed % 3 == 0:
+        t[0] = 0.0
+    t = np.unique(t)
+    angles = np.column_stack([rng.uniform(-np.pi, np.pi, len(t)),
+                              rng.uniform(-np.pi / 2, np.pi / 2, len(t))])
+    chief = np.concatenate([rng.uniform([-1.3, -1.0, -0.3], [1.3, 1.0, 0.3]),
+                            rng.normal(0, 0.3, 3)])
+    m = int(rng.integers(1, 260))
+    scale = 10.0 ** rng.uniform(-4, 0, (m, 1))
+    xs = chief + scale * rng.normal(0, 1, (m, 6))
+    sigma = float(10.0 ** rng.uniform(-6, -2))
+    return mu, h, t, angles, chief, xs, sigma, seed % 2
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_problems_parity(torch_dev, seed):
+    """Propagated states bitwise and costs within 1e-11 on random problems
+    (every mass ratio class, off-grid times, non-multiple-of-64 swarms,
+    particles far from the chief and near the primaries)."""
+    torch, dev = torch_dev
+    mu, hs, t, angles, chief, xs, sigma, mode = random_problem(seed)
+    h = iod.iod_create(mu, chief, t, angles, sigma, h=hs, cost_mode=mode)
+    P = oracle.Problem(mu, hs, sigma, chief, t, angles, mode)
+    m = len(xs)
+    x = to_dev(torch, dev, xs)
+    st = torch.full((len(t), 6, x.shape[1]), -7.0, dtype=torch.float64, device=dev)
+    iod.iod_propagate(h, x, m, st)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    for i in range(m):
+        want = oracle.propagate(mu, hs, xs[i], t)
+        assert np.array_equal(got[:, :, i], want, equal_nan=True), (seed, i)
+    assert_cost_parity(gpu_cost(torch, dev, h, xs), oracle.cost(P, xs))
+
+
 def test_eval_parity_c1_full_size_sampled(torch_dev):
     """The full single-swarm workload (65,536 particles, 40 observations over
     4000 steps) in one launch, as the benchmark runs it; the oracle checks a
