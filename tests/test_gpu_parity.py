@@ -210,6 +210,32 @@ def test_random_problems_parity(torch_dev, seed):
     assert_cost_parity(gpu_cost(torch, dev, h, xs), oracle.cost(P, xs))
 
 
+def test_random_problems_batch_solve(torch_dev):
+    """The 20 random problems as one batch (each with its own mass ratio,
+    step, cost mode, observation count and swarm size), 8 iterations of
+    Algorithm 1: every problem's global best equals the oracle's run of it
+    alone (state bitwise, cost and history within 1e-11)."""
+    probs = [random_problem(seed) for seed in range(20)]
+    rng = np.random.default_rng(78)
+    boxes = [10.0 ** rng.uniform(-3, -1) for _ in probs]
+    b = iod.iod_create_batch([q[0] for q in probs], [q[4] for q in probs], [q[2] for q in probs],
+                             [q[3] for q in probs], [q[6] for q in probs],
+                             h=[q[1] for q in probs], cost_mode=[q[7] for q in probs])
+    m = np.array([len(q[5]) for q in probs], dtype=np.int64)
+    params = [iod.pso_params(0.7, 1.5, 1.5, 11, q[4] - w, q[4] + w, problem=p)
+              for p, (q, w) in enumerate(zip(probs, boxes))]
+    n_iter = 8
+    g, J, hist = iod.iod_batch_solve(b, params, m, n_iter)
+    for p, (q, w) in enumerate(zip(probs, boxes)):
+        mu, hs, t, angles, chief, _, sigma, mode = q
+        P = oracle.Problem(mu, hs, sigma, chief, t, angles, mode)
+        S = oracle.Pso(0.7, 1.5, 1.5, 11, chief - w, chief + w, problem=p)
+        g_ref, J_ref, h_ref, _ = oracle.pso_solve(P, S, int(m[p]), n_iter)
+        assert np.array_equal(g[p], g_ref), p
+        assert abs(J[p] - J_ref) <= COST_RTOL * abs(J_ref), (p, J[p], J_ref)
+        assert np.all(np.abs(hist[p] - h_ref) <= COST_RTOL * np.abs(h_ref)), p
+
+
 def test_eval_parity_c1_full_size_sampled(torch_dev):
     """The full single-swarm workload (65,536 particles, 40 observations over
     4000 steps) in one launch, as the benchmark runs it; the oracle checks a
