@@ -88,6 +88,39 @@ def test_adjoint_matches_oracle_stm(torch_dev, mode, case):
     print(f"{case} mode {mode}: adjoint vs STM max rel err {worst:.2e}")
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_adjoint_random_problems(torch_dev, seed):
+    """Adjoint against the oracle's STM gradient on seeded random problems:
+    every mass-ratio class, a random step, on- and off-grid observation
+    times (sometimes one at the epoch), both cost modes, particles 1e-4 to
+    1e-2 from a random truth."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng([79, seed])
+    mu = [0.0, 1e-30, 0.012150585, float(rng.uniform(0, 0.5)), 0.5][seed % 5]
+    hs = [1e-3, 5e-4, float(rng.uniform(2e-4, 2e-3))][seed % 3]
+    K = int(rng.integers(1, 50))
+    T = float(rng.uniform(0.05, 0.6))
+    t = np.unique(np.where(rng.random(K) < 0.5, np.round(rng.uniform(0, T, K) / hs) * hs,
+                           rng.uniform(0, T, K)))
+    if seed % 2 == 0:
+        t[0] = 0.0
+    t = np.unique(t)
+    chief = np.concatenate([rng.uniform([0.7, -0.3, -0.2], [1.3, 0.3, 0.2]), rng.normal(0, 0.2, 3)])
+    truth = chief + rng.uniform(-5e-3, 5e-3, 6)
+    mode = seed % 2
+    P0 = oracle.Problem(mu, hs, 1e-5, chief, t, np.zeros((len(t), 2)), mode)
+    obs = oracle.predict(P0, truth) + rng.normal(0, 1e-5, (len(t), 2))
+    P = P0.with_angles(obs)
+    h = iod.iod_create(mu, chief, t, obs, 1e-5, h=hs, cost_mode=mode)
+    xs = truth + 10.0 ** rng.uniform(-4, -2, (24, 1)) * rng.normal(0, 1, (24, 6))
+    cost, g = gpu_grad(torch, dev, h, xs)
+    assert np.all(np.abs(cost - oracle.cost(P, xs)) <= 1e-11 * np.abs(oracle.cost(P, xs)))
+    for i, xi in enumerate(xs):
+        gs, _ = oracle.grad(P, xi)
+        rel = np.max(np.abs(g[i] - gs)) / np.max(np.abs(gs))
+        assert rel <= 1e-9, (seed, i, rel)
+
+
 def test_adjoint_matches_central_fd(torch_dev):
     torch, dev = torch_dev
     wl = W.c0(1)
