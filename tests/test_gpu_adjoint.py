@@ -88,13 +88,11 @@ def test_adjoint_matches_oracle_stm(torch_dev, mode, case):
     print(f"{case} mode {mode}: adjoint vs STM max rel err {worst:.2e}")
 
 
-@pytest.mark.parametrize("seed", range(8))
-def test_adjoint_random_problems(torch_dev, seed):
-    """Adjoint against the oracle's STM gradient on seeded random problems:
-    every mass-ratio class, a random step, on- and off-grid observation
-    times (sometimes one at the epoch), both cost modes, particles 1e-4 to
-    1e-2 from a random truth."""
-    torch, dev = torch_dev
+def random_problem(seed, mode):
+    """A seeded random problem: any mass-ratio class, a random step, on- and
+    off-grid observation times (sometimes one at the epoch), observed angles
+    of a random truth plus noise, and 24 particles 1e-4 to 1e-2 from that
+    truth. Returns the oracle problem, the library handle and the particles."""
     rng = np.random.default_rng([79, seed])
     mu = [0.0, 1e-30, 0.012150585, float(rng.uniform(0, 0.5)), 0.5][seed % 5]
     hs = [1e-3, 5e-4, float(rng.uniform(2e-4, 2e-3))][seed % 3]
@@ -107,12 +105,19 @@ def test_adjoint_random_problems(torch_dev, seed):
     t = np.unique(t)
     chief = np.concatenate([rng.uniform([0.7, -0.3, -0.2], [1.3, 0.3, 0.2]), rng.normal(0, 0.2, 3)])
     truth = chief + rng.uniform(-5e-3, 5e-3, 6)
-    mode = seed % 2
     P0 = oracle.Problem(mu, hs, 1e-5, chief, t, np.zeros((len(t), 2)), mode)
     obs = oracle.predict(P0, truth) + rng.normal(0, 1e-5, (len(t), 2))
-    P = P0.with_angles(obs)
     h = iod.iod_create(mu, chief, t, obs, 1e-5, h=hs, cost_mode=mode)
     xs = truth + 10.0 ** rng.uniform(-4, -2, (24, 1)) * rng.normal(0, 1, (24, 6))
+    return P0.with_angles(obs), h, xs
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_adjoint_random_problems(torch_dev, seed):
+    """Adjoint against the oracle's STM gradient on seeded random problems
+    (both cost modes)."""
+    torch, dev = torch_dev
+    P, h, xs = random_problem(seed, seed % 2)
     cost, g = gpu_grad(torch, dev, h, xs)
     assert np.all(np.abs(cost - oracle.cost(P, xs)) <= 1e-11 * np.abs(oracle.cost(P, xs)))
     for i, xi in enumerate(xs):
@@ -173,6 +178,29 @@ def test_normal_equations_match_oracle_jacobian(torch_dev):
         assert np.max(np.abs(jtr[:, i] - J.T @ r)) <= 1e-9 * np.max(np.abs(J.T @ r))
         # the adjoint (least-squares cost) gives twice J^T r
         assert np.max(np.abs(g[:, i] - 2 * jtr[:, i])) <= 1e-9 * np.max(np.abs(g[:, i]))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_normal_equations_random_problems(torch_dev, seed):
+    """chi2, J^T J and J^T r from the forward tangent against the oracle's
+    residuals and residual Jacobian on the seeded random problems."""
+    torch, dev = torch_dev
+    P, h, xs = random_problem(seed, 1)
+    x = cols(torch, dev, xs)
+    ld = x.shape[1]
+    chi2 = torch.zeros(ld, dtype=torch.float64, device=dev)
+    jtj = torch.zeros((21, ld), dtype=torch.float64, device=dev)
+    jtr = torch.zeros((6, ld), dtype=torch.float64, device=dev)
+    iod.iod_normal_eq(h, x, len(xs), chi2, jtj, jtr)
+    torch.cuda.synchronize()
+    chi2, jtj, jtr = chi2.cpu().numpy(), jtj.cpu().numpy(), jtr.cpu().numpy()
+    iu = np.triu_indices(6)
+    for i, xi in enumerate(xs):
+        r, J = oracle.residuals(P, xi, jacobian=True)
+        assert abs(chi2[i] - r @ r) <= 1e-11 * (r @ r), (seed, i)
+        N = J.T @ J
+        assert np.max(np.abs(jtj[:, i] - N[iu])) <= 1e-9 * np.max(np.abs(N)), (seed, i)
+        assert np.max(np.abs(jtr[:, i] - J.T @ r)) <= 1e-9 * np.max(np.abs(J.T @ r)), (seed, i)
 
 
 def lsq_reference(P, x0):
