@@ -214,7 +214,8 @@ def test_random_problems_batch_solve(torch_dev):
     """The 20 random problems as one batch (each with its own mass ratio,
     step, cost mode, observation count and swarm size), 8 iterations of
     Algorithm 1: every problem's global best equals the oracle's run of it
-    alone (state bitwise, cost and history within 1e-11)."""
+    alone (state bitwise, cost and history within 1e-11). Then the mixed
+    path's FP64 re-evaluation of every particle after initialisation."""
     probs = [random_problem(seed) for seed in range(20)]
     rng = np.random.default_rng(78)
     boxes = [10.0 ** rng.uniform(-3, -1) for _ in probs]
@@ -234,6 +235,17 @@ def test_random_problems_batch_solve(torch_dev):
         assert np.array_equal(g[p], g_ref), p
         assert abs(J[p] - J_ref) <= COST_RTOL * abs(J_ref), (p, J[p], J_ref)
         assert np.all(np.abs(hist[p] - h_ref) <= COST_RTOL * np.abs(h_ref)), p
+    # the mixed-precision path with every particle re-evaluated in FP64: after
+    # initialisation its global best is the FP64 argmin of the initial swarm
+    m256 = np.minimum(m, 256)
+    g, J, _ = iod.iod_batch_solve_mixed(b, params, m256, 1, top_k=256)
+    for p, (q, w) in enumerate(zip(probs, boxes)):
+        mu, hs, t, angles, chief, _, sigma, mode = q
+        P = oracle.Problem(mu, hs, sigma, chief, t, angles, mode)
+        S = oracle.Pso(0.7, 1.5, 1.5, 11, chief - w, chief + w, problem=p)
+        ref = oracle.pso_init(P, S, int(m256[p]))
+        assert np.array_equal(g[p], ref.g), p
+        assert abs(J[p] - ref.jg.value) <= COST_RTOL * abs(ref.jg.value), p
 
 
 def test_eval_parity_c1_full_size_sampled(torch_dev):
