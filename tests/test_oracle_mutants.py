@@ -54,20 +54,43 @@ MUTANTS = {
                               "c[0] = (uint64_t)i; c[1] = (uint64_t)n;"),
 }
 
+# mutants of the sensitivity and variant code, run against those pins
+MUTANTS_SENS_VARIANTS = {
+    # tangent of the RK4 map and residual Jacobians
+    "jacobian_coriolis_sign": ("A[6 * 3 + 4] = 2.0;", "A[6 * 3 + 4] = -2.0;"),
+    "jacobian_power": ("e2 = 3.0 * mu / pow(r2, 5);", "e2 = 3.0 * mu / pow(r2, 3);"),
+    "tangent_stage_weight": ("const double wt[4] = {1.0, 2.0, 2.0, 1.0};",
+                             "const double wt[4] = {1.0, 2.0, 1.0, 1.0};"),
+    "azimuth_gradient_sign": ("ga[0] = rho[1] / rxy2;", "ga[0] = -rho[1] / rxy2;"),
+    "elevation_gradient_sign": ("gb[2] = -rxy / r2;", "gb[2] = rxy / r2;"),
+    # range measurement
+    "range_weight_is_one_over_sigma": (
+        "T->wr = P->ranges ? 1.0 / (P->sigma_range * P->sigma_range) : 0.0;",
+        "T->wr = P->ranges ? 1.0 / P->sigma_range : 0.0;"),
+    "range_residual_sign": ("const double dr = T->ranges[k] - range_of(rho);",
+                            "const double dr = T->ranges[k] + range_of(rho);"),
+    # constriction, grid initialisation, per-dimension coefficients, Algorithm 2
+    "constriction_formula": ("return 2.0 / fabs(2.0 - phi - sqrt(phi * phi - 4.0 * phi));",
+                             "return 2.0 / fabs(2.0 - phi - sqrt(phi * phi - 2.0 * phi));"),
+    "grid_levels_off_by_one": ("if (G / b * (b + 1) > m) break;",
+                               "if (G / b * (b + 1) >= m) break;"),
+    "per_dimension_word": ("a1[d] = S->eta1 * u01(u[2 * d]);", "a1[d] = S->eta1 * u01(u[d]);"),
+    "algorithm2_lag": ("orc_tolerance_met(hist[n], hist[n - S->tol_lag], S->tol))",
+                       "orc_tolerance_met(hist[n], hist[n - S->tol_lag + 1], S->tol))"),
+}
+
 CHILD = """
 import sys
 sys.path.insert(0, {root!r})
 import oracle
 oracle._LIB = {lib!r}
 import pytest
-sys.exit(pytest.main(["-q", "-x", "-p", "no:cacheprovider", {tests!r}]))
+sys.exit(pytest.main(["-q", "-x", "-p", "no:cacheprovider", *{tests!r}]))
 """
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_pins_catch_planted_mistake(tmp_path, name):
+def run_mutant(tmp_path, name, old, new, test_files):
     import oracle
-    old, new = MUTANTS[name]
     src = open(oracle._SRC).read()
     assert src.count(old) == 1, f"{name}: the text to mutate must occur exactly once"
     mutant = tmp_path / "orc_mutant.c"
@@ -77,7 +100,7 @@ def test_pins_catch_planted_mistake(tmp_path, name):
                     "-o", lib, str(mutant), "-lm"], check=True, capture_output=True)
     env = dict(os.environ, OMP_NUM_THREADS="4")
     code = CHILD.format(root=ROOT, lib=lib,
-                        tests=os.path.join(ROOT, "tests", "test_oracle_pins.py"))
+                        tests=[os.path.join(ROOT, "tests", t) for t in test_files])
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                        timeout=600)
     # 1: a pin failed; a negative code: the mutant crashed the run. 0 would
@@ -85,3 +108,14 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     assert r.returncode == 1 or r.returncode < 0, (name, r.returncode, r.stdout[-2000:])
     failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
     print(name, "->", failed[:1])
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    run_mutant(tmp_path, name, *MUTANTS[name], ["test_oracle_pins.py"])
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS_SENS_VARIANTS))
+def test_sensitivity_and_variant_pins_catch_planted_mistake(tmp_path, name):
+    run_mutant(tmp_path, name, *MUTANTS_SENS_VARIANTS[name],
+               ["test_oracle_sensitivity.py", "test_oracle_variants.py"])

@@ -217,7 +217,7 @@ def test_per_dimension_weights_from_philox(orc):
     of counters (n, i, problem, 2..4) drawn from numpy's Philox."""
     wl = W.c0(0)
     P = noise_free(orc, wl)
-    m = 8
+    m = 64
     S = orc.Pso(0.0, 0.0, 1.0, 11, wl.lo, wl.hi, problem=2, flags=orc.PSO_PER_DIM_R)
     s = orc.pso_init(P, S, m)
     x0, g0 = s.x.copy(), s.g.copy()
@@ -226,21 +226,22 @@ def test_per_dimension_weights_from_philox(orc):
         w = np.concatenate([numpy_philox_block([1, i, 2, 2 + b], [11, 0]) for b in range(3)])
         want = np.array([u01(w[2 * d + 1]) * (g0[d] - x0[i, d]) for d in range(6)])
         assert np.array_equal(s.v[i], want), i
-    # and with eta1 only, words 2d (personal best = initial state at n = 1,
-    # so iterate twice and check the second iteration's cognitive pull)
+    # and with eta1 only, words 2d: after iteration 1 (no pull yet, p = x),
+    # every personal best is set to the noise-free truth (cost exactly 0), so
+    # iteration 2 keeps it and pulls each particle by r1_d (truth_d - x_d)
     S1 = orc.Pso(0.0, 1.0, 0.0, 11, wl.lo, wl.hi, problem=2, flags=orc.PSO_PER_DIM_R)
     s = orc.pso_init(P, S1, m)
     orc.pso_iterate(P, S1, s, 1)
     assert np.all(s.v == 0)
-    s.cost[:] = np.inf   # not used at n >= 2: the oracle re-evaluates
+    s.p[:] = wl.truth
+    s.jp[:] = 0.0
     x1 = s.x.copy()
-    p1 = s.p.copy()
+    assert np.all(orc.cost(P, x1) > 0.0)
     orc.pso_iterate(P, S1, s, 1)
-    jx1 = orc.cost(P, x1)
     for i in range(m):
-        pb = x1[i] if jx1[i] < orc.cost(P, p1[i:i + 1])[0] else p1[i]
         w = np.concatenate([numpy_philox_block([2, i, 2, 2 + b], [11, 0]) for b in range(3)])
-        want = np.array([u01(w[2 * d]) * (pb[d] - x1[i, d]) for d in range(6)])
+        want = np.array([u01(w[2 * d]) * (wl.truth[d] - x1[i, d]) for d in range(6)])
+        assert np.all(want != 0)
         assert np.array_equal(s.v[i], want), i
 
 
