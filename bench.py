@@ -40,6 +40,7 @@ FLOP_PER_UPDATE = 50     # PSO velocity/position update of one particle
 FLOP_PER_RANGE = 10      # range term: |rho| (5 flops + 1 sqrt), residual, weight and fma
 PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
+PEAK_CLOCK_GHZ = 2.4     # the clock the published peaks assume
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
 # sources the FP64 iteration kernel is built from
@@ -61,18 +62,35 @@ def kernel_hash() -> str:
 
 def load_counters():
     """From the committed rocprofv3 counter summary of the iteration kernel:
-    calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE) and FP64
-    operations per evaluating launch ((2 FMA + MUL + ADD) x 64); None for
-    both if the kernel sources changed since the counters were taken."""
+    calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE), FP64
+    operations per evaluating launch ((2 FMA + MUL + ADD) x 64), VALU
+    instructions per wave per RK4 step and the clock during the launch; None
+    for all if the kernel sources changed since the counters were taken."""
+    none = (None, None, None, None)
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
     except OSError:
-        return None, None
+        return none
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel_sha") != kernel_hash():
-        return None, None
-    return float(kv["hbm_bytes_per_launch"]), float(kv["total_64_ops_per_eval_launch"])
+        return none
+    return (float(kv["hbm_bytes_per_launch"]), float(kv["total_64_ops_per_eval_launch"]),
+            float(kv["valu_per_wave_step"]), float(kv["clock_ghz"]))
+
+
+def contract_ceiling(valu_per_step, clock_ghz, frac):
+    """The fraction of FP64 peak the arithmetic contract allows: one RK4 step
+    is FLOP_PER_STEP algorithmic flop-equivalents but valu_per_step issue
+    slots, which the peak counts as 2 flops each (FMA); at the measured
+    clock the ceiling scales by clock / 2.4 GHz."""
+    if valu_per_step is None:
+        return None
+    at_peak_clock = FLOP_PER_STEP / (2.0 * valu_per_step)
+    at_clock = at_peak_clock * clock_ghz / PEAK_CLOCK_GHZ
+    return {"valu_per_wave_step": valu_per_step, "frac_at_2.4GHz_full_issue": at_peak_clock,
+            "clock_ghz_measured": clock_ghz, "frac_at_measured_clock": at_clock,
+            "achieved_over_ceiling_at_measured_clock": frac / at_clock}
 
 
 # The paper's variants beside Algorithm 1 (all off in the default run).
@@ -519,7 +537,8 @@ def main():
     ps_per_solve = n_run * wl.m * steps_per_eval
     value = args.steps * ps_per_solve / elapsed
 
-    traffic, ops64 = load_counters() if (args.workload == "c1" and args.variant == "none") else (None, None)
+    traffic, ops64, valu_step, clock = (load_counters() if (args.workload == "c1" and args.variant == "none")
+                                        else (None, None, None, None))
     counter_tflops = (ops64 * (n_run - 1) / n_run / avg_launch_s / 1e12) if ops64 else None
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -542,11 +561,16 @@ def main():
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "median_eval_launch_ms": med_eval_ms,
                      "flop_per_launch": flop_launch,
-                     # second reading: FP64 operations counted by the hardware
-                     # (profiles/k_swarm_iter_c1_fp64.md) over the same launches
+                     # second reading, instruction throughput: FP64 operations counted
+                     # by the hardware (profiles/k_swarm_iter_c1_fp64.md) over the same
+                     # launches, Newton steps of sqrt and division included
                      "counter_achieved": counter_tflops,
                      "counter_frac": (counter_tflops / PEAK_FP64_TFLOPS
-                                      if counter_tflops is not None else None)},
+                                      if counter_tflops is not None else None),
+                     # the ceiling that correctly rounded sqrt and division (bitwise
+                     # parity with the oracle) put on the algorithmic fraction
+                     "contract_ceiling": contract_ceiling(valu_step, clock,
+                                                          achieved / PEAK_FP64_TFLOPS)},
     }
     if args.variant == "none":
         # the FP32 half of the metric on the same problem and swarm

@@ -260,16 +260,20 @@ int iod_swarm_init(iod_handle *h, iod_swarm *s, const iod_pso_params *p, void *s
 int iod_step(iod_handle *h, iod_swarm *s, const iod_pso_params *p, int64_t n_iter,
              void *stream);
 
-/* Global best after s->iter iterations: host outputs best_state [6],
- * *best_cost and *best_index (any may be NULL). Writes hist[s->iter] when
- * hist is given. Synchronises `stream`.
+/* Global best after s->iter iterations (Algorithm 1, the global-best update
+ * after the particle loop: the lowest personal best, lowest index on ties,
+ * replaces the previous global best only if strictly lower): host outputs
+ * best_state [6], *best_cost and *best_index (any may be NULL). Writes
+ * hist[s->iter] when hist is given. Synchronises `stream`.
  * Errors: IOD_EINVAL, IOD_ESTATE, IOD_EDEVICE. */
 int iod_swarm_best(iod_handle *h, iod_swarm *s, double best_state[6], double *best_cost,
                    int64_t *best_index, void *stream);
 
-/* Whole solve: allocate an m-particle swarm, initialise, run n_iter
- * iterations (fewer if Algorithm 2 ends the run), return the global best,
- * free. history (host [n_iter + 1] or NULL) receives the global-best cost
+/* Whole solve of Algorithm 1 (initialisation, n_iter iterations of the
+ * evaluate / personal-best / velocity-position loop with the global-best
+ * update after each, as iod_swarm_init + iod_step + iod_swarm_best):
+ * allocate an m-particle swarm, initialise, run n_iter iterations (fewer if
+ * Algorithm 2 ends the run), return the global best, free. history (host [n_iter + 1] or NULL) receives the global-best cost
  * after initialisation and after each iteration (NaN after an Algorithm 2
  * stop). Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,

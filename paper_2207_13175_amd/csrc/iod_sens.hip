@@ -213,7 +213,7 @@ __device__ __forceinline__ void obs_cotangent(const KArgs &A, const double *row,
     for (int d = 0; d < 6; ++d) add[d] = sbar[d];
 }
 
-constexpr int CKPT = 64;   // steps between adjoint checkpoints
+constexpr int CKPT = ADJ_CKPT;   // steps between adjoint checkpoints (the host sizes the scratch with it)
 
 // Cost and its gradient by the discrete adjoint. Forward: the certified
 // propagation and cost (same bits as k_eval), checkpoints X_{64 j}. Reverse:
