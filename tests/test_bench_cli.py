@@ -16,11 +16,15 @@ def test_more_than_one_gpu_is_refused():
 def test_counter_record_is_tied_to_the_kernel_sources():
     sys.path.insert(0, ROOT)
     import bench
-    traffic, ops = bench.load_counters()
+    traffic, ops, valu, clock = bench.load_counters()
     # the committed record either matches the current sources or is ignored
     with open(bench.TRAFFIC_FILE) as f:
         sha = [l.split(":", 1)[1].strip() for l in f if l.startswith("kernel_sha")][0]
     if sha == bench.kernel_hash():
-        assert traffic > 0 and ops > 0
+        assert traffic > 0 and ops > 0 and valu > 0 and clock > 0
+        c = bench.contract_ceiling(valu, clock, 0.29)
+        # 186 flop-eq per step over two flops per issue slot, scaled by the clock
+        assert abs(c["frac_at_2.4GHz_full_issue"] - 186 / (2 * valu)) < 1e-12
+        assert c["frac_at_measured_clock"] < c["frac_at_2.4GHz_full_issue"] <= 1.0
     else:
-        assert traffic is None and ops is None
+        assert traffic is None and ops is None and valu is None and clock is None
