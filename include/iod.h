@@ -454,6 +454,24 @@ int64_t iod_grad_work_len(const iod_handle *h, int64_t ld);
 int iod_grad(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost, double *grad,
              double *work, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): iod_grad
+ * with its workspace taken from a static device array of
+ * IOD_NOALLOC_SCRATCH_DOUBLES doubles (32 MiB), which each GPU holds from
+ * library load until the process ends. Same kernels, same results as
+ * iod_grad. The call performs no allocation of any kind (no hipMalloc, no
+ * library allocation); its first call on a device looks up that device's
+ * copy of the array. It needs iod_grad_work_len(h, ld) <= the array: sizes
+ * beyond it return IOD_EINVAL (use iod_grad with a caller workspace).
+ * Every call on one GPU shares that GPU's array: calls that may overlap
+ * there (other streams, other threads, other handles) race and must be
+ * serialised by the caller; calls on one stream are ordered. The array's
+ * contents are whatever the last call left (nothing needs to start at zero).
+ * Arguments and errors otherwise as iod_grad. */
+#define IOD_NOALLOC_SCRATCH_DOUBLES ((int64_t)1 << 22)
+int iod_grad_noalloc(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost,
+                     double *grad, void *stream);
+
 /* Gauss-Newton normal equations of the whitened residuals from the forward
  * tangent (6x6 state transition matrix) of the RK4 propagation:
  *   chi2 device [ld]: sum of r^2

@@ -122,6 +122,8 @@ _SIGNATURES = {
     "iod_grad_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
     "iod_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "iod_grad_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]),
     "iod_normal_eq": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "iod_polish_work_len": (C.c_int64, [C.c_void_p, C.c_int64]),
@@ -564,6 +566,17 @@ def iod_grad(handle: Handle, x, m, cost, grad, work=None, stream=None):
         work = _workspace(_check(lib().iod_grad_work_len(handle.ptr, ld)), x.device)
     _check(lib().iod_grad(handle.ptr, _dev(x, (6, ld)), ld, int(m), _dev(cost, (ld,)),
                           _dev(grad, (6, ld)), _dev(work), _stream(stream)))
+
+
+def iod_grad_noalloc(handle: Handle, x, m, cost, grad, stream=None):
+    """As iod_grad, with the library's static device scratch as the workspace
+    (no allocation in the library or here)."""
+    ld = x.shape[1]
+    _check(lib().iod_grad_noalloc(handle.ptr, _dev(x, (6, ld)), ld, int(m), _dev(cost, (ld,)),
+                                  _dev(grad, (6, ld)), _stream(stream)))
+
+
+IOD_NOALLOC_SCRATCH_DOUBLES = 1 << 22
 
 
 def iod_normal_eq(handle: Handle, x, m, chi2, jtj, jtr, stream=None):

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -1449,6 +1450,35 @@ void single_cols(const iod_handle *h, const double *x, int64_t ld, int64_t m, in
     B.nprob = 1;
 }
 
+// Static device scratch of iod_grad_noalloc (adjoint checkpoints and segment
+// states), for callers that cannot allocate. Each device holds its own copy
+// from module load until the process ends. In host code `scratch` names only
+// a host-side stand-in: its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// ever handed to a kernel.
+static __device__ __align__(256) double scratch[IOD_NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+int noalloc_scratch(int device, double **out)
+{
+    static std::mutex mu;
+    static double *addr[NOALLOC_MAX_DEVICES] = {};
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return fail(IOD_EDEVICE, "device %d beyond the %d the static scratch tracks", device,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(IOD_EDEVICE, "hipGetSymbolAddress(scratch) gave a null address");
+        addr[device] = (double *)p;
+    }
+    *out = addr[device];
+    return IOD_OK;
+}
+
 int batch_predict_impl(iod_batch *b, const double *x, double *out, bool ranges)
 {
     int rc = check_batch(b);
@@ -1497,7 +1527,9 @@ int64_t iod_grad_work_len(const iod_handle *h, int64_t ld)
 {
     if (!h) return fail(IOD_EINVAL, "null handle");
     if (ld < 1 || ld > MAX_M) return fail(IOD_EINVAL, "ld out of range");
-    return adj_rows(h->P) * 6 * ld;
+    const int64_t per_col = adj_rows(h->P) * 6;
+    if (ld > INT64_MAX / per_col) return fail(IOD_EINVAL, "workspace size overflows");
+    return per_col * ld;
 }
 
 int iod_grad(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost, double *grad,
@@ -1507,6 +1539,32 @@ int iod_grad(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost
     if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, cost);
     if (rc != IOD_OK || m == 0) return rc;
     if (!grad || !work) return fail(IOD_EINVAL, "null device pointer");
+    const int bs = block_of(h->cfg);
+    ProbDesc D;
+    SwarmArrays B;
+    single_cols(h, x, ld, m, bs, D, B);
+    B.cost = cost;
+    HIP_TRY(launch_grad(D, B, bs, D.nslots, grad, work, ld, -1, (hipStream_t)stream));
+    return IOD_OK;
+}
+
+int iod_grad_noalloc(iod_handle *h, const double *x, int64_t ld, int64_t m, double *cost,
+                     double *grad, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, cost);
+    if (rc != IOD_OK || m == 0) return rc;
+    if (!grad) return fail(IOD_EINVAL, "null device pointer");
+    const int64_t per_col = adj_rows(h->P) * 6;
+    if (ld > IOD_NOALLOC_SCRATCH_DOUBLES / per_col)
+        return fail(IOD_EINVAL,
+                    "iod_grad_noalloc: %lld doubles of adjoint scratch (ld = %lld) exceed the "
+                    "static scratch of %lld doubles; use iod_grad with a workspace",
+                    (long long)per_col * (long long)ld, (long long)ld,
+                    (long long)IOD_NOALLOC_SCRATCH_DOUBLES);
+    double *work = nullptr;
+    rc = noalloc_scratch(h->device, &work);
+    if (rc != IOD_OK) return rc;
     const int bs = block_of(h->cfg);
     ProbDesc D;
     SwarmArrays B;
