@@ -505,3 +505,97 @@ def test_cost_accuracy_against_extended_precision(torch_dev, which):
           f"FP32 median {np.median(rel32):.2e} max {rel32.max():.2e}")
     assert np.median(rel[1:]) <= 1e-9
     assert rel.max() <= 1e-6
+
+
+def _oracle_pso(wl, P, m, problem=0, seed=None):
+    seed = wl.pso_seed if seed is None else seed
+    S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, seed, wl.lo, wl.hi, problem=problem)
+    params = iod.pso_params(wl.omega, wl.eta1, wl.eta2, seed, wl.lo, wl.hi, problem=problem)
+    return S, params
+
+
+@pytest.mark.parametrize("m,block", [(65536, 256), (65536, 64), (8192, 64), (1000, 128)])
+def test_global_best_handoff_many_slots(torch_dev, m, block):
+    """Algorithm 1's global-best update across many workgroups: every
+    workgroup writes its argmin slot, the next launch reduces all slots of
+    the problem (1,024 slots at block 64, so each thread of the reduction
+    walks 16 of them; 256 at block 256; 128 at block 64 in two passes) with
+    the previous record. The whole swarm is compared with the oracle after
+    initialisation and after each of 4 iterations on the small workload's
+    problem (500 RK4 steps): x, v, p bitwise, costs within the bar, and the
+    global-best index and state equal."""
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    iod.iod_set_config(h, block=block)
+    S, params = _oracle_pso(wl, P, m, seed=5)
+    print(f"m={m} block={block} slots={(m + block - 1) // block}", flush=True)
+    ref = oracle.pso_init(P, S, m)
+    sw = iod.Swarm(m, device=dev, hist_len=6)
+    iod.iod_swarm_init(h, sw, params)
+    torch.cuda.synchronize()
+    assert sw.s.block == block
+    assert_swarm_equal(sw, ref, m)
+    g, jg, gi = iod.iod_swarm_best(h, sw)
+    assert gi == ref.gi.value and np.array_equal(g, ref.g)
+    moved = 0
+    for n in range(1, 5):
+        prev = ref.gi.value
+        oracle.pso_iterate(P, S, ref, 1)
+        iod.iod_step(h, sw, params, 1)
+        torch.cuda.synchronize()
+        assert_swarm_equal(sw, ref, m)
+        g, jg, gi = iod.iod_swarm_best(h, sw)
+        assert gi == ref.gi.value and np.array_equal(g, ref.g), (n, gi, ref.gi.value)
+        assert abs(jg - ref.jg.value) <= COST_RTOL * abs(ref.jg.value)
+        moved += gi != prev
+    # the global best moved between workgroups at least once (the hand-off was exercised)
+    assert moved >= 1
+
+
+def test_global_best_handoff_batch_many_slots(torch_dev):
+    """The same hand-off in a batch: three problems of 8,192 particles at
+    block 64 (128 slots each, at slot offsets 0, 128, 256) for 4 iterations,
+    each problem's global best against the oracle's run of it alone."""
+    torch, dev = torch_dev
+    wls = [W.c0(s) for s in (0, 1, 2)]
+    probs = [make_problem(wl) for wl in wls]
+    b = iod.iod_create_batch([wl.mu for wl in wls], [wl.chief for wl in wls], [wl.t for wl in wls],
+                             [obs for _, obs in probs], [wl.sigma for wl in wls], h=wls[0].h)
+    iod.iod_batch_set_config(b, block=64, graph=1)
+    m = np.array([8192, 8192, 8192], dtype=np.int64)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, 9, wl.lo, wl.hi, problem=p)
+              for p, wl in enumerate(wls)]
+    g, J, hist = iod.iod_batch_solve(b, params, m, 4)
+    for p, (wl, (P, _)) in enumerate(zip(wls, probs)):
+        S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, 9, wl.lo, wl.hi, problem=p)
+        g_ref, J_ref, h_ref, _ = oracle.pso_solve(P, S, 8192, 4)
+        assert np.array_equal(g[p], g_ref), p
+        assert abs(J[p] - J_ref) <= COST_RTOL * abs(J_ref), p
+        assert np.all(np.abs(hist[p] - h_ref) <= COST_RTOL * np.abs(h_ref)), p
+
+
+def test_c1_full_size_iterations_oracle(torch_dev):
+    """The single large swarm itself (65,536 particles, 4,000 RK4 steps, 40
+    observations, 256 slots) for 3 iterations in the launch configuration the
+    benchmark times (block 256, one iod_step per iteration): the whole swarm
+    against the oracle after each iteration."""
+    torch, dev = torch_dev
+    wl = W.c1(0)
+    P, obs = make_problem(wl)
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    S, params = _oracle_pso(wl, P, wl.m)
+    ref = oracle.pso_init(P, S, wl.m)
+    sw = iod.Swarm(wl.m, device=dev, hist_len=4)
+    iod.iod_swarm_init(h, sw, params)
+    torch.cuda.synchronize()
+    assert_swarm_equal(sw, ref, wl.m)
+    for n in range(1, 4):
+        oracle.pso_iterate(P, S, ref, 1)
+        iod.iod_step(h, sw, params, 1)
+        torch.cuda.synchronize()
+        assert_swarm_equal(sw, ref, wl.m)
+        g, jg, gi = iod.iod_swarm_best(h, sw)
+        assert gi == ref.gi.value and np.array_equal(g, ref.g), (n, gi, ref.gi.value)
+        print(f"c1 iteration {n}: J_g {jg:.6e} at particle {gi}", flush=True)
