@@ -99,6 +99,8 @@ def _load():
     lib.orc_cost.restype = C.c_int
     lib.orc_cost_ld.argtypes = [C.POINTER(_Problem), C.c_int64, _D, _D]
     lib.orc_cost_ld.restype = C.c_int
+    lib.orc_residuals_ld.argtypes = [C.POINTER(_Problem), _D, _D]
+    lib.orc_residuals_ld.restype = C.c_int
     lib.orc_philox4x64.argtypes = [_U64, _U64, _U64]
     lib.orc_pso_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Pso), C.c_int64,
                                  _D, _D, _D, _D, _D, _D, _D, _I64]
@@ -400,6 +402,18 @@ def residuals(problem: Problem, x0, jacobian=False):
     if rc < 0:
         raise ValueError("invalid problem")
     return (r, jac) if jacobian else r
+
+
+def residuals_ld(problem: Problem, x0):
+    """Whitened residuals [R K] as ``residuals`` but evaluated in extended
+    precision from the literal formulas (the accuracy reference), rounded to
+    float64."""
+    lib = _load()
+    x0 = _f64(x0).ravel()
+    r = np.empty(problem.R * problem.K)
+    if lib.orc_residuals_ld(C.byref(problem._s), _dp(x0), _dp(r)) < 0:
+        raise ValueError("invalid problem")
+    return r
 
 
 def grad(problem: Problem, x0):

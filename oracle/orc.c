@@ -557,6 +557,55 @@ int orc_cost_ld(const orc_problem *P, int64_t m, const double *x, double *cost)
     return rc;
 }
 
+/* Whitened residuals at x0 in extended precision, rounded to binary64 on
+ * return, in the layout of orc_residuals: r[R k] = da_k / sigma,
+ * r[R k + 1] = db_k / sigma and, with ranges, r[R k + 2] = dr_k / sigma_range,
+ * with da, db and dr from the literal formulas of orc_cost_ld (so that the
+ * sum of r^2 over an observation is its e_k). Near a least-squares minimum
+ * the binary64 residuals carry the rounding of the propagation and of the
+ * deputy-chief difference (about 1e-7 of a whitened residual over a few
+ * thousand steps); these carry about 2^-11 of that, which resolves the
+ * minimiser where binary64 cannot. Returns 0, -1 on an invalid schedule, 1
+ * if some line of sight vanishes (residuals there are NaN). */
+int orc_residuals_ld(const orc_problem *P, const double x0[6], double *r)
+{
+    const int32_t K = P->n_obs;
+    const int R = P->ranges ? 3 : 2;
+    int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    double *tau = (double *)malloc(sizeof(double) * (size_t)K);
+    ld *chief = (ld *)malloc(sizeof(ld) * 6 * (size_t)K);
+    ld *st = (ld *)malloc(sizeof(ld) * 6 * (size_t)K);
+    int rc = orc_schedule(P->t, K, P->h, ns, tau);
+    if (rc == 0) {
+        const ld mu = P->mu, h = P->h;
+        const ld is = 1 / (ld)P->sigma;
+        const ld isr = P->ranges ? 1 / (ld)P->sigma_range : 0;
+        int32_t k;
+        propagate_ld(mu, h, P->chief, K, ns, tau, chief);
+        propagate_ld(mu, h, x0, K, ns, tau, st);
+        for (k = 0; k < K; k++) {
+            const ld rx = st[6 * k] - chief[6 * k], ry = st[6 * k + 1] - chief[6 * k + 1];
+            const ld rz = st[6 * k + 2] - chief[6 * k + 2];
+            const ld rn = sqrtl(rx * rx + ry * ry + rz * rz);
+            ld da = NAN, db = NAN, dr = NAN;
+            if (rn != 0) {
+                da = (ld)P->angles[2 * k] - atan2l(ry / rn, rx / rn);
+                while (da > PI_LD) da -= 2 * PI_LD;
+                while (da <= -PI_LD) da += 2 * PI_LD;
+                db = (ld)P->angles[2 * k + 1] - asinl(rz / rn);
+                if (P->ranges) dr = (ld)P->ranges[k] - rn;
+            } else {
+                rc = 1;
+            }
+            r[R * k] = (double)(da * is);
+            r[R * k + 1] = (double)(db * is);
+            if (R == 3) r[R * k + 2] = (double)(dr * isr);
+        }
+    }
+    free(ns); free(tau); free(chief); free(st);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel     */
 /* random numbers: as easy as 1, 2, 3", SC'11).                              */

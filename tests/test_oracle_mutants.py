@@ -69,6 +69,12 @@ MUTANTS_SENS_VARIANTS = {
         "T->wr = P->ranges ? 1.0 / P->sigma_range : 0.0;"),
     "range_residual_sign": ("const double dr = T->ranges[k] - range_of(rho);",
                             "const double dr = T->ranges[k] + range_of(rho);"),
+    # extended-precision residuals (the refinement's accuracy reference)
+    "ld_elevation_residual_sign": ("db = (ld)P->angles[2 * k + 1] - asinl(rz / rn);",
+                                   "db = (ld)P->angles[2 * k + 1] + asinl(rz / rn);"),
+    "ld_residual_weight": ("r[R * k] = (double)(da * is);", "r[R * k] = (double)(da / is);"),
+    "ld_range_residual_sign": ("if (P->ranges) dr = (ld)P->ranges[k] - rn;",
+                               "if (P->ranges) dr = rn - (ld)P->ranges[k];"),
     # constriction, grid initialisation, per-dimension coefficients, Algorithm 2
     "constriction_formula": ("return 2.0 / fabs(2.0 - phi - sqrt(phi * phi - 4.0 * phi));",
                              "return 2.0 / fabs(2.0 - phi - sqrt(phi * phi - 2.0 * phi));"),

@@ -87,3 +87,40 @@ def test_gradient_matches_fd_of_cost(orc, mode):
         assert abs(J - orc.cost(P, x[None, :])[0]) <= 1e-12 * J
         N = fd(lambda v: orc.cost(P, v[None, :]), x, 1e-8 * max(1.0, np.max(np.abs(x))))[0]
         assert np.max(np.abs(g - N)) <= 1e-5 * np.max(np.abs(g)), (g, N)
+
+
+def test_extended_precision_residuals(orc):
+    """The extended-precision residuals (the accuracy reference of the
+    refinement, literal formulas evaluated in x87 long double): the same
+    quantities as the binary64 residuals (azimuth, elevation and, with
+    ranges, range per observation, each over its sigma) up to the rounding of
+    the binary64 propagation, their squares summing to the extended-precision
+    least-squares cost."""
+    P, wl = problem(orc, seed=4)
+    rng = np.random.default_rng(3)
+    for P_ in (P, P.with_ranges(orc.predict_ranges(P, wl.truth) + 1e-7 * rng.standard_normal(P.K),
+                                1e-7)):
+        for scale in (0.0, 1e-6, 3e-4):
+            x = wl.truth + scale * rng.standard_normal(6)
+            r64, rld = orc.residuals(P_, x), orc.residuals_ld(P_, x)
+            assert rld.shape == r64.shape == (P_.R * P_.K,)
+            # binary64 propagation rounding is ~1e-7 of a whitened residual here
+            assert np.max(np.abs(r64 - rld)) <= 1e-5, (scale, np.max(np.abs(r64 - rld)))
+            chi2 = orc.cost_ld(P_.with_mode(orc.COST_CHI2), x[None, :])[0]
+            assert abs(np.sum(rld ** 2) - chi2) <= 1e-13 * chi2
+
+
+def test_extended_precision_least_squares_minimum_is_the_truth(orc):
+    """On noise-free observations the least-squares minimiser is the true
+    deputy state. Gauss-Newton with the binary64 Jacobian and the
+    extended-precision residuals reaches it to ~1e-13 from 1e-5 away (the
+    observations themselves, predicted in binary64, carry ~1e-13 rad)."""
+    wl = W.tiny(6, K=8, T=0.8)
+    P0 = orc.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((8, 2)), orc.COST_CHI2)
+    P = P0.with_angles(orc.predict(P0, wl.truth))
+    x = wl.truth + 1e-5 * np.array([1.0, -0.5, 0.3, 0.7, -0.2, 0.4])
+    for _ in range(12):
+        J = orc.residuals(P, x, jacobian=True)[1]
+        x = x + np.linalg.lstsq(J, -orc.residuals_ld(P, x), rcond=None)[0]
+    assert np.max(np.abs(x - wl.truth)) <= 1e-11, x - wl.truth
+    assert np.max(np.abs(orc.residuals_ld(P, x))) <= 1e-6
