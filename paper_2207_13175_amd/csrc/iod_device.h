@@ -144,10 +144,38 @@ __device__ __forceinline__ void rk4(double mu, double mu1, bool fast, double h, 
     for (int d = 0; d < 6; ++d) X[d] = fma(h6, a[d], X[d]);
 }
 
-// n steps of size h in place.
+// n steps of size h in place. The in-range sequences run all n steps with no
+// vote in between: each lane only accumulates whether every stage of every
+// step was certified, and the wave votes once at the end. If some lane was
+// not, the wave restores the state it started from and redoes the n steps on
+// the IEEE path. Either way the result is that of correctly rounded sqrt and
+// division, bit for bit, as with a vote per step; without a branch between
+// steps the scheduler can overlap one step's distance chains with the end
+// of the previous step.
 __device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6])
 {
-    for (; n > 0; --n) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, X);
+    if (A.fast) {
+        double X0[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) X0[d] = X[d];
+        bool ok = true;
+#pragma unroll 2
+        for (int32_t j = 0; j < n; ++j) {
+            double a[6];
+            ok &= rk4_sum<true>(A.mu, A.mu1, A.h, A.h2, X, a);
+#pragma unroll
+            for (int d = 0; d < 6; ++d) X[d] = fma(A.h6, a[d], X[d]);
+        }
+        if (__all(ok)) return;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) X[d] = X0[d];
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        double a[6];
+        rk4_sum<false>(A.mu, A.mu1, A.h, A.h2, X, a);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) X[d] = fma(A.h6, a[d], X[d]);
+    }
 }
 
 // Who stages the observation table into LDS together: the whole workgroup
