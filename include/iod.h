@@ -275,7 +275,10 @@ int iod_swarm_best(iod_handle *h, iod_swarm *s, double best_state[6], double *be
  * allocate an m-particle swarm, initialise, run n_iter iterations (fewer if
  * Algorithm 2 ends the run), return the global best, free. history (host [n_iter + 1] or NULL) receives the global-best cost
  * after initialisation and after each iteration (NaN after an Algorithm 2
- * stop). Synchronous. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+ * stop). Synchronous. The handle keeps the solve's stream, its swarm storage
+ * (grown when a larger swarm needs it) and the instantiated iteration graph
+ * until iod_destroy, so a repeated solve allocates and instantiates nothing.
+ * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
               double best_state[6], double *best_cost, double *history);
 
@@ -313,7 +316,8 @@ int iod_create_batch_ranged(int32_t n_problems, const double *mu, const double *
                             const double *sigma, const double *sigma_range,
                             const iod_options *opt, iod_batch **out);
 
-/* Release a batch (NULL is accepted). Synchronises the device. */
+/* Release a batch (NULL is accepted) and everything it keeps (see
+ * iod_batch_solve). Synchronises the device. */
 int iod_batch_destroy(iod_batch *b);
 
 /* Number of problems, or a negative code. */
@@ -350,7 +354,9 @@ int64_t iod_batch_offsets(const iod_batch *b, const int64_t *m, int64_t *off);
  *   x     device [6][ld], columns per iod_batch_offsets
  *   m     host [P] particles per problem (0 allowed)
  *   cost  device [ld]
- * Synchronises `stream` (the launch uses temporary device tables).
+ * Enqueued on `stream` without waiting: the launch tables (problem
+ * descriptors and work list) stay with the batch and are copied again only
+ * when m changes; calls on one batch must not overlap.
  * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
                    void *stream);
@@ -363,6 +369,10 @@ int iod_batch_eval(iod_batch *b, const double *x, int64_t ld, const int64_t *m, 
  * iod_solve on the same problem with params[p] and m[p], the variants
  * included; a problem that Algorithm 2 ends early stops taking device time
  * (its workgroups exit at once) while the others go on. Synchronous.
+ * The batch keeps its solve stream, the swarm storage, the launch tables and
+ * the instantiated iteration graphs (up to 32, keyed by every launch
+ * argument) until iod_batch_destroy, so a repeated solve of the same shape
+ * allocates and instantiates nothing.
  * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_batch_solve(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
                     double *best_states, double *best_costs, double *history);
@@ -388,7 +398,7 @@ int iod_propagate_f32(iod_handle *h, const double *x, int64_t ld, int64_t m, dou
 
 /* As iod_batch_eval, with the FP32 propagation above and the residual formed
  * from the compensated state minus the chief position split into an FP32
- * pair; e_k in FP32, J accumulated in FP64. Synchronises `stream`. */
+ * pair; e_k in FP32, J accumulated in FP64. Enqueued as iod_batch_eval. */
 int iod_batch_eval_f32(iod_batch *b, const double *x, int64_t ld, const int64_t *m, double *cost,
                        void *stream);
 
@@ -396,7 +406,8 @@ int iod_batch_eval_f32(iod_batch *b, const double *x, int64_t ld, const int64_t 
  * smallest (cost, index), NaN ranked as +inf, in ascending order.
  *   keys  device [ld], columns per iod_batch_offsets
  *   out   device [P][top_k]; entries past m[p] are -1
- * Synchronises `stream`. Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
+ * Enqueued on `stream` without waiting (tables kept as in iod_batch_eval).
+ * Errors: IOD_EINVAL, IOD_ENOMEM, IOD_EDEVICE. */
 int iod_batch_select_topk(iod_batch *b, const double *keys, int64_t ld, const int64_t *m,
                           int32_t top_k, int32_t *out, void *stream);
 
@@ -498,7 +509,8 @@ int iod_polish(iod_handle *h, double *x, int64_t ld, int64_t m, int32_t n_iter, 
                double *work, void *stream);
 
 /* Batched polish: candidates of problem p in the columns given by
- * iod_batch_offsets(m). Synchronises `stream`. */
+ * iod_batch_offsets(m). Enqueued on `stream` without waiting (tables kept as
+ * in iod_batch_eval). */
 int64_t iod_batch_polish_work_len(const iod_batch *b, int64_t ld);
 int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int32_t n_iter,
                      double *chi2, double *work, void *stream);
@@ -506,8 +518,10 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
 /* Swarm then refinement, for every problem of the batch: n_iter iterations of
  * the particle swarm (FP64 if top_k = 0, else mixed precision with top_k as
  * in iod_batch_solve_mixed), then at most n_gn damped Gauss-Newton iterations
- * on each of the problem's n_cand (1..64) lowest-cost personal bests, keeping
- * the one with the lowest chi2. Each iteration tries T = min(8, 64 / n_cand)
+ * on each of the problem's n_cand (1..64) candidates, keeping the one with
+ * the lowest chi2. The candidates are the problem's global best (decided by
+ * FP64 costs on both routes) and its lowest-cost other personal bests (by
+ * the swarm's own costs, FP32 in mixed precision), min(n_cand, m) in all. Each iteration tries T = min(8, 64 / n_cand)
  * dampings per candidate, lambda 10^(k - T/2) for k < T, each step v with its
  * geodesic-acceleration correction a (from the residuals at x + 0.1 v) added
  * as v + a/2 when 2|a| <= 0.75|v|, and keeps the trial with the lowest chi2
@@ -515,7 +529,10 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
  * is lower, 10 x the largest tried). A candidate stops
  * once its accepted step, or every trial step when none is accepted, is at
  * most 1e-12 in every component, or lambda reaches 1e12; a problem stops when
- * all its candidates have. Outputs (host): best_states [P][6], best_chi2 [P]
+ * all its candidates have. With n_gn >= 1 every candidate then takes up to
+ * two undamped Gauss-Newton steps, each applied only if no component exceeds
+ * 1e-6 (near the minimum the binary64 chi2 is too noisy to judge the last
+ * steps along weakly observed directions; the steps themselves are not). Outputs (host): best_states [P][6], best_chi2 [P]
  * (may be NULL) and best_costs [P] (the problem's own cost mode, may be
  * NULL). Synchronous. */
 int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,

@@ -270,31 +270,147 @@ struct DevBuf {
     }
 };
 
-struct Stream {
-    hipStream_t s = nullptr;
-    ~Stream()
+// Device buffer kept by a handle or batch across calls and grown on demand,
+// so that a repeated call of the same or a smaller size allocates nothing.
+// Growing frees the old buffer first (hipFree waits for the device).
+struct DevCache {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevCache() = default;
+    DevCache(const DevCache &) = delete;
+    DevCache &operator=(const DevCache &) = delete;
+    ~DevCache() { release(); }
+    void release()
     {
-        if (s) (void)hipStreamDestroy(s);
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n == 0) n = 1;
+        if (n <= bytes) return hipSuccess;
+        release();
+        Phase ph("libiod: device allocation");
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess)
+            bytes = n;
+        else
+            p = nullptr;
+        return e;
+    }
+    template <class T>
+    T *as() const
+    {
+        return (T *)p;
     }
 };
 
-struct Event {
-    hipEvent_t e = nullptr;
-    ~Event()
+// Device copy of a host table, copied (stream-ordered, from pageable host
+// memory, which the runtime stages before returning) only when its bytes
+// differ from the last copy; the last copy's bytes are kept as the shadow.
+// A table that kernels modify must not use this (its device bytes would no
+// longer match the shadow).
+struct DevTable {
+    DevCache d;
+    std::vector<unsigned char> shadow;
+    bool valid = false;
+    hipError_t upload(const void *src, size_t n, hipStream_t st)
     {
-        if (e) (void)hipEventDestroy(e);
+        if (valid && shadow.size() == n && (n == 0 || std::memcmp(shadow.data(), src, n) == 0))
+            return hipSuccess;
+        valid = false;
+        hipError_t e = d.ensure(n);
+        if (e != hipSuccess) return e;
+        shadow.assign((const unsigned char *)src, (const unsigned char *)src + n);
+        if (n) e = hipMemcpyAsync(d.p, shadow.data(), n, hipMemcpyHostToDevice, st);
+        valid = e == hipSuccess;
+        return e;
+    }
+    template <class T>
+    hipError_t upload(const std::vector<T> &v, hipStream_t st)
+    {
+        return upload(v.data(), v.size() * sizeof(T), st);
+    }
+    template <class T>
+    T *as() const
+    {
+        return d.as<T>();
+    }
+};
+
+// Bytes that identify a captured launch sequence: everything its kernel
+// arguments were built from.
+struct Key {
+    std::vector<unsigned char> b;
+    template <class T>
+    Key &add(const T &v)
+    {
+        const unsigned char *q = (const unsigned char *)&v;
+        b.insert(b.end(), q, q + sizeof v);
+        return *this;
+    }
+};
+
+// Instantiated graphs of iteration sequences, keyed by their launch
+// arguments, most recently used last; at most MAX are kept.
+struct GraphCache {
+    static constexpr size_t MAX = 32;
+    struct Entry {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> entries;
+    GraphCache() = default;
+    GraphCache(const GraphCache &) = delete;
+    GraphCache &operator=(const GraphCache &) = delete;
+    ~GraphCache() { clear(); }
+    void clear()
+    {
+        for (Entry &e : entries)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        entries.clear();
+    }
+    hipGraphExec_t find(const Key &k)
+    {
+        for (size_t i = 0; i < entries.size(); ++i)
+            if (entries[i].key == k.b) {
+                Entry e = entries[i];
+                entries.erase(entries.begin() + (long)i);
+                entries.push_back(e);
+                return e.exec;
+            }
+        return nullptr;
+    }
+    void put(const Key &k, hipGraphExec_t exec)
+    {
+        if (entries.size() >= MAX) {
+            (void)hipGraphExecDestroy(entries.front().exec);
+            entries.erase(entries.begin());
+        }
+        entries.push_back({k.b, exec});
     }
 };
 
 // Runs the iteration launches n0 + 1 .. n0 + n_iter, directly or as one
-// captured graph.
+// captured graph. With a cache, the graph is instantiated once per key
+// (which must identify every launch argument) and replayed afterwards.
 template <class F>
-int run_iterations(hipStream_t st, bool graph, int64_t n0, int64_t n_iter, F launch_one)
+int run_iterations(hipStream_t st, bool graph, int64_t n0, int64_t n_iter, F launch_one,
+                   GraphCache *cache = nullptr, Key key = Key())
 {
     if (!graph || n_iter == 0) {
         for (int64_t j = 1; j <= n_iter; ++j) HIP_TRY(launch_one(n0 + j));
         return IOD_OK;
     }
+    key.add(n0).add(n_iter);
+    if (cache) {
+        if (hipGraphExec_t ex = cache->find(key)) {
+            HIP_TRY(hipGraphLaunch(ex, st));
+            return IOD_OK;
+        }
+    }
+    Phase ph("libiod: graph capture and instantiation");
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int64_t j = 1; j <= n_iter && le == hipSuccess; ++j) le = launch_one(n0 + j);
@@ -307,10 +423,17 @@ int run_iterations(hipStream_t st, bool graph, int64_t n0, int64_t n_iter, F lau
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
     hipGraphExec_t ge = nullptr;
     hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(ge, st);
-    if (ge) (void)hipGraphExecDestroy(ge);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "hipGraph instantiate/launch");
+    ph.end();
+    if (e == hipSuccess) e = hipGraphLaunch(ge, st);
+    if (e != hipSuccess) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        return hip_fail(e, "hipGraph instantiate/launch");
+    }
+    if (cache)
+        cache->put(key, ge);
+    else
+        (void)hipGraphExecDestroy(ge);
     return IOD_OK;
 }
 
@@ -327,8 +450,18 @@ struct iod_handle {
     int32_t *d_ns = nullptr;   // [K]
     std::vector<double> rc;    // [K][3] chief positions
     iod_launch_config cfg{0, IOD_ORDER_LONGEST_FIRST, 0, 0};
+    // kept across iod_solve calls: its stream, swarm storage and graphs
+    hipStream_t stream = nullptr;
+    DevCache solve_buf;
+    GraphCache graphs;
 
     KArgs kargs() const { return kargs_of(P, d_tab, d_ns); }
+};
+
+// Buffers of the batched refinement stage, kept across calls.
+struct PolishBuffers {
+    DevCache cand, x, chi, work, best, bchi, cost, act, done, vt, jrows, live, live_count;
+    DevTable desc, edesc, tdesc, list, lanes, nn;
 };
 
 struct iod_batch {
@@ -340,6 +473,17 @@ struct iod_batch {
     int32_t *d_ns = nullptr;       // concatenated [sum K]
     iod_launch_config cfg{0, IOD_ORDER_LONGEST_FIRST, 1, 0};
     double last_iter_ms = 0.0;  // mean iteration time of the last iod_batch_solve
+    // kept across calls, so that repeated solves of one shape allocate and
+    // instantiate nothing: the solve stream and timing events, the swarm
+    // storage, the launch tables, the captured iteration graphs, and the
+    // tables of the evaluation, selection and polish calls
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevCache swarm, cand;
+    DevTable desc, work, porder;
+    GraphCache graphs;
+    DevTable eval_desc, eval_work, topk_desc, bpol_desc, bpol_work;
+    PolishBuffers pol;
 
     KArgs kargs(int32_t p) const
     {
@@ -511,6 +655,10 @@ int iod_destroy(iod_handle *h)
     if (hipSetDevice(h->device) == hipSuccess) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+        h->graphs.clear();
+        h->solve_buf.release();
+        if (h->stream) (void)hipStreamDestroy(h->stream);
+        h->stream = nullptr;
         if (h->d_tab && (e = hipFree(h->d_tab)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
         if (h->d_ns && (e = hipFree(h->d_ns)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
     }
@@ -673,11 +821,12 @@ int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
     const int64_t ld = round64(m);
     const int64_t wl = iod_swarm_work_len(m);
     const size_t total = (size_t)(20 * ld + wl + (n_iter + 1));
-    Stream st;
-    DevBuf buf;
-    HIP_TRY(hipStreamCreate(&st.s));
-    HIP_TRY(hipMalloc(&buf.p, total * sizeof(double)));
-    double *base = (double *)buf.p;
+    // the stream, the swarm storage and the captured iterations are the
+    // handle's, kept for the next call
+    if (!h->stream) HIP_TRY(hipStreamCreate(&h->stream));
+    HIP_TRY(h->solve_buf.ensure(total * sizeof(double)));
+    hipStream_t st = h->stream;
+    double *base = h->solve_buf.as<double>();
     iod_swarm s;
     std::memset(&s, 0, sizeof s);
     s.x = base;
@@ -691,22 +840,26 @@ int iod_solve(iod_handle *h, const iod_pso_params *p, int64_t m, int64_t n_iter,
     s.ld = ld;
     s.m = m;
     s.iter = -1;
-    rc = iod_swarm_init(h, &s, p, st.s);
+    rc = iod_swarm_init(h, &s, p, st);
     if (rc == IOD_OK) {
         ProbDesc D;
         SwarmArrays B;
         single_view(h, &s, p, D, B);
-        rc = run_iterations(st.s, h->cfg.graph != 0, 0, n_iter, [&](int64_t n) {
-            return launch_swarm_iter(D, B, s.block, D.nslots, n, st.s, h->cfg.waves);
-        });
+        Key key;
+        key.add(D).add(B).add(s.block).add(h->cfg.waves);
+        rc = run_iterations(st, h->cfg.graph != 0, 0, n_iter, [&](int64_t n) {
+            return launch_swarm_iter(D, B, s.block, D.nslots, n, st, h->cfg.waves);
+        }, &h->graphs, key);
         if (rc == IOD_OK) s.iter = n_iter;
     }
-    if (rc == IOD_OK) rc = iod_swarm_best(h, &s, best_state, best_cost, nullptr, st.s);
+    if (rc == IOD_OK) rc = iod_swarm_best(h, &s, best_state, best_cost, nullptr, st);
     if (rc == IOD_OK && history) {
-        hipError_t e = hipMemcpy(history, s.hist, (size_t)(n_iter + 1) * sizeof(double), hipMemcpyDeviceToHost);
+        hipError_t e = hipMemcpyAsync(history, s.hist, (size_t)(n_iter + 1) * sizeof(double),
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy history");
     }
-    (void)hipStreamSynchronize(st.s);
+    (void)hipStreamSynchronize(st);
     return rc;
 }
 
@@ -800,6 +953,12 @@ int iod_batch_destroy(iod_batch *b)
     if (hipSetDevice(b->device) == hipSuccess) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+        b->graphs.clear();
+        if (b->ev0) (void)hipEventDestroy(b->ev0);
+        if (b->ev1) (void)hipEventDestroy(b->ev1);
+        if (b->stream) (void)hipStreamDestroy(b->stream);
+        b->ev0 = b->ev1 = nullptr;
+        b->stream = nullptr;
         if (b->d_tab && (e = hipFree(b->d_tab)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
         if (b->d_ns && (e = hipFree(b->d_ns)) != hipSuccess && rc == IOD_OK) rc = hip_fail(e, "hipFree");
     }
@@ -910,7 +1069,7 @@ struct PolishStage {
     double *best_states, *best_chi2, *best_costs;  // host [P][6], [P], [P]
 };
 int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
-                     const PolishStage &S, hipStream_t st);
+                     const PolishStage &S, const double *final_recs, hipStream_t st);
 
 int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int64_t n_iter,
               const iod_launch_config &cfg, double *best_states, double *best_costs,
@@ -924,28 +1083,25 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     Phase swarm_phase(top_k ? "iod_batch: mixed-precision swarm" : "iod_batch: FP64 swarm");
     const int64_t P = b->P, ld = L.ld;
     const size_t nd = (size_t)(20 * ld + 2 * L.total_slots * REC + 2 * P * REC + P * (n_iter + 1) + P);
-    Stream st;
-    DevBuf dbuf, ddesc, dwork, dcand, dpord;
-    HIP_TRY(hipStreamCreate(&st.s));
-    HIP_TRY(hipMalloc(&dbuf.p, nd * sizeof(double)));
-    if (top_k > 0) HIP_TRY(hipMalloc(&dcand.p, (size_t)P * top_k * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&dpord.p, (size_t)P * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(dpord.p, L.porder.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice, st.s));
-    int32_t *cand = (int32_t *)dcand.p;
-    double *base = (double *)dbuf.p;
+    // stream, storage and tables are the batch's, kept for the next call
+    if (!b->stream) HIP_TRY(hipStreamCreate(&b->stream));
+    hipStream_t st = b->stream;
+    HIP_TRY(b->swarm.ensure(nd * sizeof(double)));
+    if (top_k > 0) HIP_TRY(b->cand.ensure((size_t)P * top_k * sizeof(int32_t)));
+    HIP_TRY(b->porder.upload(L.porder, st));
+    int32_t *cand = b->cand.as<int32_t>();
+    double *base = b->swarm.as<double>();
     double *hist = base + 20 * ld + 2 * L.total_slots * REC + 2 * P * REC;
     double *stop = hist + P * (n_iter + 1);
     for (int64_t p = 0; p < P; ++p) {
         L.descs[p].hist = hist + p * (n_iter + 1);
         L.descs[p].hist_len = n_iter + 1;
     }
-    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st.s));
-    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st.s));
+    HIP_TRY(b->desc.upload(L.descs, st));
+    HIP_TRY(b->work.upload(L.work, st));
     SwarmArrays B;
-    B.desc = (const ProbDesc *)ddesc.p;
-    B.work = (const int32_t *)dwork.p;
+    B.desc = b->desc.as<const ProbDesc>();
+    B.work = b->work.as<const int32_t>();
     B.x = base;
     B.v = base + 6 * ld;
     B.p = base + 12 * ld;
@@ -954,59 +1110,63 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     B.slots = base + 20 * ld;
     B.recs = B.slots + 2 * L.total_slots * REC;
     B.stop = stop;
-    B.porder = (const int32_t *)dpord.p;
+    B.porder = b->porder.as<const int32_t>();
     B.ld = ld;
     B.total_slots = L.total_slots;
     B.nprob = P;
     const ProbDesc &d0 = L.descs[0];
     // one iteration: FP64 fused launch, or FP32 launch + top-k + FP64 re-evaluation
     auto iterate = [&](int64_t n) -> hipError_t {
-        if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st.s, cfg.waves);
-        hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, st.s);
-        if (e == hipSuccess) e = launch_topk(B, B.jp, top_k, cand, st.s);
-        if (e == hipSuccess) e = launch_reeval64(B, cand, top_k, n, st.s);
+        if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st, cfg.waves);
+        hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, st);
+        if (e == hipSuccess) e = launch_topk(B, B.jp, top_k, cand, st);
+        if (e == hipSuccess) e = launch_reeval64(B, cand, top_k, n, st);
         return e;
     };
     if (top_k == 0) {
-        HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st.s));
+        HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st));
     } else {
-        HIP_TRY(launch_mixed_init(d0, B, bs, L.grid, st.s));
-        HIP_TRY(launch_topk(B, B.jp, top_k, cand, st.s));
-        HIP_TRY(launch_reeval64(B, cand, top_k, 0, st.s));
+        HIP_TRY(launch_mixed_init(d0, B, bs, L.grid, st));
+        HIP_TRY(launch_topk(B, B.jp, top_k, cand, st));
+        HIP_TRY(launch_reeval64(B, cand, top_k, 0, st));
     }
-    Event e0, e1;
     if (iter_ms) {
-        HIP_TRY(hipEventCreate(&e0.e));
-        HIP_TRY(hipEventCreate(&e1.e));
+        if (!b->ev0) HIP_TRY(hipEventCreate(&b->ev0));
+        if (!b->ev1) HIP_TRY(hipEventCreate(&b->ev1));
         // the first iteration reuses the initial evaluation: run it untimed
         HIP_TRY(iterate(1));
-        HIP_TRY(hipEventRecord(e0.e, st.s));
+        HIP_TRY(hipEventRecord(b->ev0, st));
     }
     const int64_t n0 = iter_ms ? 1 : 0;
-    rc = run_iterations(st.s, cfg.graph != 0, n0, n_iter - n0, iterate);
+    // the graph's launches read the descriptors, work list and problem order
+    // from device tables (refreshed above when they change); the key holds
+    // every launch argument
+    Key key;
+    key.add(d0).add(B).add(bs).add(L.grid).add(cfg.waves).add(top_k).add(cand);
+    rc = run_iterations(st, cfg.graph != 0, n0, n_iter - n0, iterate, &b->graphs, key);
     if (rc == IOD_OK && iter_ms) {
-        hipError_t e = hipEventRecord(e1.e, st.s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1.e);
+        hipError_t e = hipEventRecord(b->ev1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
         float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0.e, e1.e);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
         if (e != hipSuccess) rc = hip_fail(e, "iteration timing");
         *iter_ms = n_iter > n0 ? ms / (double)(n_iter - n0) : 0.0;
     }
     if (rc == IOD_OK && top_k == 0) {
-        hipError_t e = launch_swarm_final(d0, B, n_iter, st.s);
+        hipError_t e = launch_swarm_final(d0, B, n_iter, st);
         if (e != hipSuccess) rc = hip_fail(e, "final launch");
     }
     if (rc == IOD_OK && stage) {
-        HIP_TRY(hipStreamSynchronize(st.s));
+        HIP_TRY(hipStreamSynchronize(st));
         swarm_phase.end();
         Phase refine_phase("iod_batch: refinement");
-        rc = polish_stage_run(b, L, B, *stage, st.s);
+        rc = polish_stage_run(b, L, B, *stage, B.recs + (n_iter & 1) * P * REC, st);
     }
     if (rc == IOD_OK && (best_states || best_costs)) {
         std::vector<double> recs((size_t)P * REC);
         hipError_t e = hipMemcpyAsync(recs.data(), B.recs + (n_iter & 1) * P * REC, recs.size() * sizeof(double),
-                                      hipMemcpyDeviceToHost, st.s);
-        if (e == hipSuccess) e = hipStreamSynchronize(st.s);
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "read-back");
         for (int64_t p = 0; p < P; ++p) {
             if (best_states) std::memcpy(best_states + 6 * p, &recs[p * REC + 2], 6 * sizeof(double));
@@ -1015,11 +1175,11 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     }
     if (rc == IOD_OK && history) {
         hipError_t e = hipMemcpyAsync(history, hist, (size_t)P * (n_iter + 1) * sizeof(double),
-                                      hipMemcpyDeviceToHost, st.s);
-        if (e == hipSuccess) e = hipStreamSynchronize(st.s);
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "history read-back");
     }
-    hipError_t e = hipStreamSynchronize(st.s);
+    hipError_t e = hipStreamSynchronize(st);
     if (rc == IOD_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
     return rc;
 }
@@ -1081,16 +1241,13 @@ int iod_batch_select_topk(iod_batch *b, const double *keys, int64_t ld, const in
     if (ld < L.ld) return fail(IOD_EINVAL, "ld = %lld < %lld", (long long)ld, (long long)L.ld);
     if (!keys || !out) return fail(IOD_EINVAL, "null device pointer");
     hipStream_t st = (hipStream_t)stream;
-    DevBuf ddesc;
-    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
-    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(b->topk_desc.upload(L.descs, st));
     SwarmArrays B;
     std::memset(&B, 0, sizeof B);
-    B.desc = (const ProbDesc *)ddesc.p;
+    B.desc = b->topk_desc.as<const ProbDesc>();
     B.ld = ld;
     B.nprob = b->P;
     HIP_TRY(launch_topk(B, keys, top_k, out, st));
-    HIP_TRY(hipStreamSynchronize(st));
     return IOD_OK;
 }
 
@@ -1126,15 +1283,14 @@ int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m,
     if (L.grid == 0) return IOD_OK;
     if (!x || !cost) return fail(IOD_EINVAL, "null device pointer");
     hipStream_t st = (hipStream_t)stream;
-    DevBuf ddesc, dwork;
-    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    // the launch tables are the batch's, copied only when they change, so the
+    // call returns without waiting for the device
+    HIP_TRY(b->eval_desc.upload(L.descs, st));
+    HIP_TRY(b->eval_work.upload(L.work, st));
     SwarmArrays B;
     std::memset(&B, 0, sizeof B);
-    B.desc = (const ProbDesc *)ddesc.p;
-    B.work = (const int32_t *)dwork.p;
+    B.desc = b->eval_desc.as<const ProbDesc>();
+    B.work = b->eval_work.as<const int32_t>();
     B.x = const_cast<double *>(x);
     B.cost = cost;
     B.ld = ld;
@@ -1144,7 +1300,6 @@ int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m,
         HIP_TRY(launch_eval32(L.descs[0], B, bs, L.grid, st));
     else
         HIP_TRY(launch_eval(L.descs[0], B, bs, L.grid, st));
-    HIP_TRY(hipStreamSynchronize(st));
     return IOD_OK;
 }
 
@@ -1273,14 +1428,15 @@ int polish_run(const ProbDesc &d0, SwarmArrays B, int bs, int64_t grid, int32_t 
 // descriptors (n[p] * T columns); jrows the candidates' rows of J.
 constexpr double POLISH_STEP_TOL = 1e-12;
 
+constexpr double GN_FINAL_MAX_STEP = 1e-6;  // largest component of a final undamped step
 constexpr double GEO_HD = 0.1;      // finite-difference step along v, as a fraction of v
 constexpr double GEO_ALPHA = 0.75;  // accept the correction a if 2 |a| <= alpha |v|
 
 int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
                       const int32_t *n, int64_t P, int32_t T, int32_t n_iter, double *chi2,
                       double *work, double *vt, double *jrows, int32_t n_cand, int32_t *active,
-                      int32_t *done, const int32_t *lanes, int64_t nlanes, int64_t ld,
-                      hipStream_t st)
+                      int32_t *done, const int32_t *lanes, int64_t nlanes, int32_t *live,
+                      int64_t *live_count, int64_t ld, hipStream_t st)
 {
     const int64_t jld = P * n_cand;
     double *jtj = work;
@@ -1299,62 +1455,89 @@ int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
     TB.x = xt;
     TB.cost = chi2t;
     // the normal equations and the gradient see only the candidates: packed,
-    // several problems' candidates to a wave
+    // several problems' candidates to a wave, problems with the most RK4
+    // steps first. Each iteration they take only the live pairs (problem
+    // active, candidate not done), compacted in that order after the select
+    // step, so retired pairs leave the waves; the grid stays that of all
+    // pairs and the waves past the live count exit at once.
     Lanes KL;
     KL.pairs = lanes;
     KL.n = nlanes;
+    Lanes LL;
+    LL.pairs = live;
+    LL.n = nlanes;
+    LL.count = live_count;
     const int64_t kgrid = (nlanes + 63) / 64;
+    HIP_TRY(launch_live_lanes(lanes, nlanes, active, done, live, live_count, st));
     for (int32_t it = 0; it < n_iter; ++it) {
-        HIP_TRY(launch_normal(d0, PB, 64, kgrid, chi2, jtj, jtr, st, jrows, n_cand, jld, KL));
+        HIP_TRY(launch_normal(d0, PB, 64, kgrid, chi2, jtj, jtr, st, jrows, n_cand, jld, LL));
         SwarmArrays GB = PB;
         GB.cost = cost;
-        HIP_TRY(launch_grad(d0, GB, 64, kgrid, g, adj, ld, 1, st, KL));
+        HIP_TRY(launch_grad(d0, GB, 64, kgrid, g, adj, ld, 1, st, LL));
         HIP_TRY(launch_gn_trials(x, jtj, g, lam, n, active, done, T, P, ld, xt, vt, st));
         HIP_TRY(launch_geo(PB.desc, x, jtj, jtr, jrows, n_cand, jld, lam, n, active, done, T, P,
                            ld, GEO_HD, GEO_ALPHA, vt, xt, st));
         HIP_TRY(launch_eval(d0, TB, 64, P, st));
         HIP_TRY(launch_gn_select(x, chi2, lam, done, active, xt, chi2t, n, T, P, ld,
                                  POLISH_STEP_TOL, st));
+        if (it + 1 < n_iter)
+            HIP_TRY(launch_live_lanes(lanes, nlanes, active, done, live, live_count, st));
     }
-    if (n_iter == 0) HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st));
+    if (n_iter == 0) {
+        HIP_TRY(launch_normal(d0, PB, 64, P, chi2, jtj, jtr, st));
+        return IOD_OK;
+    }
+    // Every candidate, retired or not, then takes up to two undamped
+    // Gauss-Newton steps where they are small (the second removes what the
+    // first leaves of the residuals' curvature): near the minimum the damped
+    // iterations stop where binary64 chi2 noise hides the remaining decrease
+    // along weakly observed directions, while the step itself, from the
+    // normal equations, still resolves the minimiser. chi2 is then evaluated
+    // at the final states.
+    SwarmArrays AB = PB;
+    AB.active = nullptr;
+    for (int f = 0; f < 2; ++f) {
+        HIP_TRY(launch_normal(d0, AB, 64, kgrid, chi2, jtj, jtr, st, nullptr, 0, 0, KL));
+        HIP_TRY(launch_gn_final(x, jtj, jtr, n, P, ld, GN_FINAL_MAX_STEP, st));
+    }
+    AB.cost = chi2;
+    HIP_TRY(launch_eval(d0, AB, 64, P, st));
     return IOD_OK;
 }
 
 int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
-                     const PolishStage &S, hipStream_t st)
+                     const PolishStage &S, const double *final_recs, hipStream_t st)
 {
     const int64_t P = b->P, stride = 64, ldp = P * stride;
     int64_t rows = 0;
     for (const HostProblem &Pb : b->probs) rows = std::max(rows, adj_rows(Pb));
     // trials per candidate: the free lanes of the problem's 64-lane wave, at most 8
     const int32_t T = std::max(1, std::min(8, 64 / S.n_cand));
-    DevBuf dcand, dx, dchi, dwork, ddesc, dlist, dn, dbest, dbchi, dcost, dedesc, dtdesc, dact,
-        ddone, dvt, djrows, dlanes;
     // rows of J of every candidate: max over problems of K R (R = 3 with ranges, else 2)
     int64_t jrow_max = 0;
     for (const HostProblem &Pb : b->probs)
         jrow_max = std::max<int64_t>(jrow_max, (int64_t)Pb.K * (Pb.sigma_range > 0 ? 3 : 2));
-    HIP_TRY(hipMalloc(&dcand.p, (size_t)P * S.n_cand * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&dx.p, (size_t)6 * ldp * sizeof(double)));
-    HIP_TRY(hipMalloc(&dchi.p, (size_t)ldp * sizeof(double)));
-    HIP_TRY(hipMalloc(&dwork.p, (size_t)(POLISH_COLS + rows * 6) * ldp * sizeof(double)));
-    HIP_TRY(hipMalloc(&ddesc.p, (size_t)P * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dedesc.p, (size_t)P * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dlist.p, (size_t)P * 2 * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&dn.p, (size_t)P * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&dbest.p, (size_t)6 * P * sizeof(double)));
-    HIP_TRY(hipMalloc(&dbchi.p, (size_t)P * sizeof(double)));
-    HIP_TRY(hipMalloc(&dcost.p, (size_t)P * sizeof(double)));
-    HIP_TRY(hipMalloc(&dtdesc.p, (size_t)P * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dact.p, (size_t)P * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&ddone.p, (size_t)ldp * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&dvt.p, (size_t)6 * ldp * sizeof(double)));
-    HIP_TRY(hipMalloc(&djrows.p, (size_t)jrow_max * 6 * P * S.n_cand * sizeof(double)));
-    // candidates: the swarm's best personal bests
-    HIP_TRY(launch_topk(B, B.jp, S.n_cand, (int32_t *)dcand.p, st));
-    HIP_TRY(launch_gather(B, (const int32_t *)dcand.p, S.n_cand, (double *)dx.p, ldp, stride, st));
+    // the stage's buffers are the batch's, grown when needed and kept
+    PolishBuffers &Q = b->pol;
+    HIP_TRY(Q.cand.ensure((size_t)P * S.n_cand * sizeof(int32_t)));
+    HIP_TRY(Q.x.ensure((size_t)6 * ldp * sizeof(double)));
+    HIP_TRY(Q.chi.ensure((size_t)ldp * sizeof(double)));
+    HIP_TRY(Q.work.ensure((size_t)(POLISH_COLS + rows * 6) * ldp * sizeof(double)));
+    HIP_TRY(Q.best.ensure((size_t)6 * P * sizeof(double)));
+    HIP_TRY(Q.bchi.ensure((size_t)P * sizeof(double)));
+    HIP_TRY(Q.cost.ensure((size_t)P * sizeof(double)));
+    HIP_TRY(Q.act.ensure((size_t)P * sizeof(int32_t)));
+    HIP_TRY(Q.done.ensure((size_t)ldp * sizeof(int32_t)));
+    HIP_TRY(Q.vt.ensure((size_t)6 * ldp * sizeof(double)));
+    HIP_TRY(Q.jrows.ensure((size_t)jrow_max * 6 * P * S.n_cand * sizeof(double)));
+    // candidates: each problem's global best, then its best personal bests
+    // (in the mixed-precision swarm the first is decided by FP64 costs, the
+    // ranking of the others by FP32 costs)
+    HIP_TRY(launch_topk(B, B.jp, S.n_cand, Q.cand.as<int32_t>(), st));
+    HIP_TRY(launch_gather(B, Q.cand.as<const int32_t>(), S.n_cand, final_recs, Q.x.as<double>(),
+                          ldp, stride, st));
     std::vector<ProbDesc> pd(L.descs), ed(L.descs), td(L.descs);
-    std::vector<int32_t> list(2 * P), n(P), act(P, 1), dn0(ldp, 0);
+    std::vector<int32_t> list(2 * P), n(P);
     for (int64_t p = 0; p < P; ++p) {
         ProbDesc &D = pd[p];
         D.m = std::min<int64_t>(S.n_cand, L.descs[p].m);
@@ -1376,11 +1559,11 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
         list[2 * p + 1] = 0;
         n[p] = (int32_t)D.m;
     }
-    HIP_TRY(hipMemcpyAsync(ddesc.p, pd.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dedesc.p, ed.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dlist.p, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dn.p, n.data(), n.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dtdesc.p, td.data(), P * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(Q.desc.upload(pd, st));
+    HIP_TRY(Q.edesc.upload(ed, st));
+    HIP_TRY(Q.list.upload(list, st));
+    HIP_TRY(Q.nn.upload(n, st));
+    HIP_TRY(Q.tdesc.upload(td, st));
     // packed lanes: (problem, candidate), problems with the most RK4 steps first
     std::vector<int32_t> by_steps(P);
     std::iota(by_steps.begin(), by_steps.end(), 0);
@@ -1395,38 +1578,43 @@ int polish_stage_run(iod_batch *b, const BatchLayout &L, const SwarmArrays &B,
             lanes.push_back(j);
         }
     const int64_t nlanes = (int64_t)lanes.size() / 2;
-    HIP_TRY(hipMalloc(&dlanes.p, lanes.size() * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(dlanes.p, lanes.data(), lanes.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dact.p, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ddone.p, dn0.data(), dn0.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(Q.lanes.upload(lanes, st));
+    HIP_TRY(Q.live.ensure(std::max<size_t>(lanes.size(), 2) * sizeof(int32_t)));
+    HIP_TRY(Q.live_count.ensure(sizeof(int64_t)));
+    // the retirement flags start cleared on every call (the kernels change them)
+    HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)Q.act.p, 1, (size_t)P, st));
+    HIP_TRY(hipMemsetAsync(Q.done.p, 0, (size_t)ldp * sizeof(int32_t), st));
     SwarmArrays PB;
     std::memset(&PB, 0, sizeof PB);
-    PB.desc = (const ProbDesc *)ddesc.p;
-    PB.work = (const int32_t *)dlist.p;
-    PB.x = (double *)dx.p;
+    PB.desc = Q.desc.as<const ProbDesc>();
+    PB.work = Q.list.as<const int32_t>();
+    PB.x = Q.x.as<double>();
     PB.ld = ldp;
     PB.nprob = P;
-    int rc = polish_trials_run(pd[0], PB, (const ProbDesc *)dtdesc.p, (const int32_t *)dn.p, P, T,
-                               S.n_gn, (double *)dchi.p, (double *)dwork.p, (double *)dvt.p,
-                               (double *)djrows.p, S.n_cand, (int32_t *)dact.p,
-                               (int32_t *)ddone.p, (const int32_t *)dlanes.p, nlanes, ldp, st);
+    int rc = polish_trials_run(pd[0], PB, Q.tdesc.as<const ProbDesc>(), Q.nn.as<const int32_t>(), P,
+                               T, S.n_gn, Q.chi.as<double>(), Q.work.as<double>(),
+                               Q.vt.as<double>(), Q.jrows.as<double>(), S.n_cand,
+                               Q.act.as<int32_t>(), Q.done.as<int32_t>(),
+                               Q.lanes.as<const int32_t>(), nlanes, Q.live.as<int32_t>(),
+                               Q.live_count.as<int64_t>(), ldp, st);
     if (rc != IOD_OK) return rc;
-    HIP_TRY(launch_pick_best((const double *)dx.p, (const double *)dchi.p, (const int32_t *)dn.p, P,
-                             ldp, stride, (double *)dbest.p, (double *)dbchi.p, st));
+    HIP_TRY(launch_pick_best(Q.x.as<const double>(), Q.chi.as<const double>(),
+                             Q.nn.as<const int32_t>(), P, ldp, stride, Q.best.as<double>(),
+                             Q.bchi.as<double>(), st));
     // the problem's own cost of each polished best
     SwarmArrays EB;
     std::memset(&EB, 0, sizeof EB);
-    EB.desc = (const ProbDesc *)dedesc.p;
-    EB.work = (const int32_t *)dlist.p;
-    EB.x = (double *)dbest.p;
-    EB.cost = (double *)dcost.p;
+    EB.desc = Q.edesc.as<const ProbDesc>();
+    EB.work = Q.list.as<const int32_t>();
+    EB.x = Q.best.as<double>();
+    EB.cost = Q.cost.as<double>();
     EB.ld = P;
     EB.nprob = P;
     HIP_TRY(launch_eval(ed[0], EB, 64, P, st));
     std::vector<double> best(6 * P), bchi(P), bcost(P);
-    HIP_TRY(hipMemcpyAsync(best.data(), dbest.p, best.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(bchi.data(), dbchi.p, bchi.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(bcost.data(), dcost.p, bcost.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(best.data(), Q.best.p, best.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bchi.data(), Q.bchi.p, bchi.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bcost.data(), Q.cost.p, bcost.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int64_t p = 0; p < P; ++p) {
         for (int d = 0; d < 6; ++d) S.best_states[6 * p + d] = best[d * P + p];
@@ -1637,26 +1825,21 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
     if (!x || !chi2 || !work) return fail(IOD_EINVAL, "null device pointer");
     for (ProbDesc &D : L.descs) D.k.mode = IOD_COST_CHI2;
     hipStream_t st = (hipStream_t)stream;
-    DevBuf ddesc, dwork;
-    HIP_TRY(hipMalloc(&ddesc.p, L.descs.size() * sizeof(ProbDesc)));
-    HIP_TRY(hipMalloc(&dwork.p, L.work.size() * sizeof(int32_t)));
-    HIP_TRY(hipMemcpyAsync(ddesc.p, L.descs.data(), L.descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(dwork.p, L.work.data(), L.work.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(b->bpol_desc.upload(L.descs, st));
+    HIP_TRY(b->bpol_work.upload(L.work, st));
     SwarmArrays B;
     std::memset(&B, 0, sizeof B);
-    B.desc = (const ProbDesc *)ddesc.p;
-    B.work = (const int32_t *)dwork.p;
+    B.desc = b->bpol_desc.as<const ProbDesc>();
+    B.work = b->bpol_work.as<const int32_t>();
     B.x = x;
     B.ld = ld;
     B.nprob = b->P;
-    rc = polish_run(L.descs[0], B, bs, L.grid, n_iter, chi2, work, ld, st);
-    if (rc != IOD_OK) return rc;
-    HIP_TRY(hipStreamSynchronize(st));
-    return IOD_OK;
+    return polish_run(L.descs[0], B, bs, L.grid, n_iter, chi2, work, ld, st);
 }
 
-// Mixed-precision PSO, then the Gauss-Newton polish of each problem's n_cand
-// best personal bests (by FP32 cost), keeping the best polished candidate.
+// PSO (FP64 or mixed precision), then the Gauss-Newton polish of n_cand
+// candidates per problem (its global best and its best other personal
+// bests), keeping the best polished candidate.
 int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,
                              int64_t n_iter, int32_t top_k, int32_t n_cand, int32_t n_gn,
                              double *best_states, double *best_chi2, double *best_costs)

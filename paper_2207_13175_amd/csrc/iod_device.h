@@ -600,7 +600,7 @@ __device__ __forceinline__ bool place(const ProbDesc &d0, const SwarmArrays &B, 
 {
     if (PLACE == PLACE_PACKED) {
         const int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x;
-        if (q >= L.n) return false;
+        if (q >= (L.count ? *L.count : L.n)) return false;
         p = L.pairs[2 * q];
         i = L.pairs[2 * q + 1];
         D = &B.desc[p];

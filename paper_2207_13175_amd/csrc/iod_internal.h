@@ -82,6 +82,7 @@ struct SwarmArrays {
 struct Lanes {
     const int32_t *pairs = nullptr;
     int64_t n = 0;
+    const int64_t *count = nullptr;  // device: the number of valid pairs (overrides n when set)
 };
 
 // Largest top-k of the mixed-precision ranking.

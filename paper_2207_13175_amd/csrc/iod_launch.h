@@ -92,11 +92,24 @@ hipError_t launch_geo(const ProbDesc *descs, const double *x, const double *jtj,
                       const int32_t *n, const int32_t *active, const int32_t *done, int32_t T,
                       int64_t nprob, int64_t ld, double hd, double alpha, const double *vt,
                       double *xt, hipStream_t st);
+// The pairs of lanes [n][2] whose problem is active and candidate not done,
+// in order, into out [n][2]; their number into *count (device).
+hipError_t launch_live_lanes(const int32_t *lanes, int64_t n, const int32_t *active,
+                            const int32_t *done, int32_t *out, int64_t *count, hipStream_t st);
+// Undamped Gauss-Newton step of each candidate (column p * 64 + j, j < n[p])
+// from the normal equations jtj, jtr at x, applied in place where no
+// component exceeds max_step.
+hipError_t launch_gn_final(double *x, const double *jtj, const double *jtr, const int32_t *n,
+                          int64_t nprob, int64_t ld, double max_step, hipStream_t st);
 hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done, int32_t *active,
                             const double *xt, const double *chi2t, const int32_t *n, int32_t T,
                             int64_t nprob, int64_t ld, double step_tol, hipStream_t st);
-hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k, double *dst,
-                         int64_t dld, int64_t stride, hipStream_t st);
+// Candidates of the refinement (stride <= 64, top_k <= stride): rec null,
+// the personal bests cand[p][j]; else the global best rec[p] first, then the
+// personal bests in rank order without its duplicate, top_k columns in all.
+hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k,
+                         const double *rec, double *dst, int64_t dld, int64_t stride,
+                         hipStream_t st);
 hipError_t launch_pick_best(const double *x, const double *chi2, const int32_t *n, int64_t nprob,
                             int64_t ld, int64_t stride, double *best, double *best_chi2,
                             hipStream_t st);

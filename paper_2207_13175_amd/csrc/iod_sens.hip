@@ -704,20 +704,132 @@ __global__ __launch_bounds__(64) void k_gn_select(double *__restrict__ x, double
     if (!__any(live) && j == 0) active[p] = 0;
 }
 
-// Candidate gather: column (p * stride + j) of dst gets the personal best of
-// particle cand[p][j] of problem p (or, past the selected candidates, a copy
-// of the first one so every column holds a valid state).
+// Live lanes of the refinement's packed launches: the (problem, candidate)
+// pairs of lanes [n][2] (problems with the most RK4 steps first) whose
+// problem is active and whose candidate is not done, in the same order, into
+// out; *count receives their number. One 1024-thread workgroup walks the
+// list in chunks, each wave compacting its lanes with a ballot and the
+// workgroup adding the waves' totals.
+__global__ __launch_bounds__(1024) void k_live_lanes(const int32_t *__restrict__ lanes, int64_t n,
+                                                     const int32_t *__restrict__ active,
+                                                     const int32_t *__restrict__ done,
+                                                     int32_t *__restrict__ out,
+                                                     int64_t *__restrict__ count)
+{
+    __shared__ int32_t wave_total[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+        const int64_t q = c0 + threadIdx.x;
+        int32_t p = 0, j = 0;
+        bool live = false;
+        if (q < n) {
+            p = lanes[2 * q];
+            j = lanes[2 * q + 1];
+            live = active[p] && !done[(int64_t)p * 64 + j];
+        }
+        const uint64_t mask = __ballot(live);
+        const int before = lane == 0 ? 0 : __popcll(mask & (~0ull >> (64 - lane)));
+        if (lane == 0) wave_total[wave] = __popcll(mask);
+        __syncthreads();
+        int64_t off = base;
+        for (int w = 0; w < wave; ++w) off += wave_total[w];
+        int64_t total = 0;
+        for (int w = 0; w < 16; ++w) total += wave_total[w];
+        if (live) {
+            out[2 * (off + before)] = p;
+            out[2 * (off + before) + 1] = j;
+        }
+        base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+// Final undamped Gauss-Newton step of the batched refinement, one 64-lane
+// workgroup per problem, candidate j < n[p] in column p * 64 + j: solves
+// J^T J dx = -J^T r and moves the candidate by dx if every component of dx
+// is at most max_step (the quadratic region of the minimum, where a
+// Gauss-Newton step is accurate). Near a least-squares minimum the binary64
+// chi2 carries rounding noise (about 1e-8 of its value) above the decrease
+// of a step along a weakly observed direction, so the damped iterations,
+// which keep a trial only if its chi2 is lower, stop wherever the noise hides
+// further progress; the normal equations' right-hand side J^T r is far less
+// affected, so this step lands on the minimiser.
+__global__ __launch_bounds__(64) void k_gn_final(double *__restrict__ x,
+                                                 const double *__restrict__ jtj,
+                                                 const double *__restrict__ jtr,
+                                                 const int32_t *__restrict__ n, int64_t ld,
+                                                 double max_step)
+{
+    const int64_t p = blockIdx.x;
+    const int j = threadIdx.x;
+    if (j >= n[p]) return;
+    const int64_t c = p * 64 + j;
+    double r[6];
+    if (!damped_step(jtj, jtr, ld, c, 1.0, 0.0, r)) return;
+    bool small = true;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) small = small && fabs(r[d]) <= max_step;
+    if (!small) return;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) x[d * ld + c] += r[d];
+}
+
+// Candidate gather of the refinement: columns p * stride + j of dst, j <
+// stride <= 64 (one wave per problem). Without rec, column j holds the
+// personal best of particle cand[p][j]. With rec (each problem's final
+// global-best record, [nprob][REC]), column 0 holds the global best itself,
+// whatever rank its personal best has: in the mixed-precision swarm the
+// global best is decided by FP64 costs while the personal bests rank by FP32
+// costs, so it need not be among them. The next columns take the selected
+// personal bests in rank order, skipping one whose state equals the global
+// best's bit for bit; the count stays that of the selected candidates, so
+// the lowest-ranked one drops out when the global best was not among them.
+// Columns past the candidates repeat column 0, so every column holds a valid
+// state.
 __global__ __launch_bounds__(64) void k_gather(SwarmArrays B, const int32_t *__restrict__ cand,
-                                               int32_t top_k, double *__restrict__ dst,
-                                               int64_t dld, int64_t stride)
+                                               int32_t top_k, const double *__restrict__ rec,
+                                               double *__restrict__ dst, int64_t dld,
+                                               int64_t stride)
 {
     const int64_t p = blockIdx.x;
     const ProbDesc &D = B.desc[p];
-    for (int j = threadIdx.x; j < stride; j += blockDim.x) {
-        int32_t i = j < top_k ? cand[p * top_k + j] : -1;
-        if (i < 0) i = cand[p * top_k];
-        if (i < 0) i = 0;
-        for (int d = 0; d < 6; ++d) dst[d * dld + p * stride + j] = B.p[d * B.ld + D.off + i];
+    const int j = threadIdx.x;
+    const int32_t i = j < top_k ? cand[p * top_k + j] : -1;
+    const bool has = i >= 0;
+    int32_t i0 = cand[p * top_k];
+    if (i0 < 0) i0 = 0;
+    double s[6], s0[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        s[d] = B.p[d * B.ld + D.off + (has ? i : i0)];
+        s0[d] = B.p[d * B.ld + D.off + i0];
+    }
+    const int nvalid = __popcll(__ballot(has));
+    const double *r = rec ? rec + p * REC : nullptr;
+    const bool use_rec = r && r[1] >= 0.0;
+    int col = has ? j : -1;
+    if (use_rec) {
+        bool dup = has;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            s0[d] = r[2 + d];
+            dup = dup && __double_as_longlong(s[d]) == __double_as_longlong(s0[d]);
+        }
+        const uint64_t keep = __ballot(has && !dup);
+        const uint64_t below = j == 0 ? 0ull : (keep & (~0ull >> (64 - j)));
+        col = (has && !dup) ? 1 + __popcll(below) : -1;
+        if (col >= nvalid) col = -1;
+    }
+    if (col >= 0 && col < stride) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) dst[d * dld + p * stride + col] = s[d];
+    }
+    // column 0 (the global best) and the columns past the candidates
+    if (j < stride && ((use_rec && j == 0) || j >= nvalid)) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) dst[d * dld + p * stride + j] = s0[d];
     }
 }
 
@@ -849,10 +961,26 @@ hipError_t launch_gn_select(double *x, double *chi2, double *lam, int32_t *done,
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k, double *dst,
-                         int64_t dld, int64_t stride, hipStream_t st)
+hipError_t launch_live_lanes(const int32_t *lanes, int64_t n, const int32_t *active,
+                            const int32_t *done, int32_t *out, int64_t *count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)B.nprob), dim3(64), 0, st, B, cand, top_k, dst, dld, stride);
+    hipLaunchKernelGGL(k_live_lanes, dim3(1), dim3(1024), 0, st, lanes, n, active, done, out, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gn_final(double *x, const double *jtj, const double *jtr, const int32_t *n,
+                          int64_t nprob, int64_t ld, double max_step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gn_final, dim3((unsigned)nprob), dim3(64), 0, st, x, jtj, jtr, n, ld, max_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const SwarmArrays &B, const int32_t *cand, int32_t top_k,
+                         const double *rec, double *dst, int64_t dld, int64_t stride,
+                         hipStream_t st)
+{
+    if (stride > 64 || top_k > stride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)B.nprob), dim3(64), 0, st, B, cand, top_k, rec, dst, dld, stride);
     return hipGetLastError();
 }
 

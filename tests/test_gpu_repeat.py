@@ -1,0 +1,121 @@
+"""Repeated calls on one handle or batch reuse its kept stream, storage,
+launch tables and instantiated iteration graphs. Whatever changes between
+calls (swarm sizes, PSO parameters, iteration counts, launch configuration)
+must reach the device: every result equals that of a fresh handle or batch,
+bit for bit, in any call order."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2207_13175_amd as iod
+from paper_2207_13175_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def _obs(wl):
+    P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((wl.K, 2)))
+    return oracle.predict(P0, wl.truth) + wl.noise
+
+
+def test_repeated_single_solves_match_fresh_handles(torch_dev):
+    wl = W.c0(3)
+    obs = _obs(wl)
+    calls = [(7, 300, 6), (8, 300, 6), (7, 100, 4), (7, 300, 6), (9, 700, 5)]
+
+    def solve(h, seed, m, n):
+        return iod.iod_solve(h, iod.pso_params(0.7, 1.5, 1.5, seed, wl.lo, wl.hi), m, n)
+
+    for graph in (1, 0):
+        h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+        iod.iod_set_config(h, block=128, graph=graph)
+        for seed, m, n in calls:
+            g, J, hist = solve(h, seed, m, n)
+            f = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+            iod.iod_set_config(f, block=128, graph=graph)
+            g2, J2, hist2 = solve(f, seed, m, n)
+            iod.iod_destroy(f)
+            assert np.array_equal(g, g2) and J == J2 and np.array_equal(hist, hist2), (graph, seed, m, n)
+
+
+def test_repeated_batch_solves_match_fresh_batches(torch_dev):
+    wls = [W.c0(s) for s in (0, 1, 2)]
+    obs = [_obs(wl) for wl in wls]
+
+    def make():
+        b = iod.iod_create_batch([wl.mu for wl in wls], [wl.chief for wl in wls],
+                                 [wl.t for wl in wls], obs, [wl.sigma for wl in wls], h=wls[0].h)
+        iod.iod_batch_set_config(b, block=64, graph=1)
+        return b
+
+    def params(seed):
+        return [iod.pso_params(0.7, 1.5, 1.5, seed, wl.lo, wl.hi, problem=p)
+                for p, wl in enumerate(wls)]
+
+    calls = [("fp64", 3, [300, 200, 100], 6), ("fp64", 4, [300, 200, 100], 6),
+             ("mixed", 3, [300, 200, 100], 6), ("fp64", 3, [100, 400, 64], 5),
+             ("fp64", 3, [300, 200, 100], 6), ("mixed", 5, [100, 400, 64], 7)]
+    b = make()
+
+    def run(bb, kind, seed, m, n):
+        m = np.array(m, dtype=np.int64)
+        if kind == "fp64":
+            return iod.iod_batch_solve(bb, params(seed), m, n)
+        return iod.iod_batch_solve_mixed(bb, params(seed), m, n, top_k=32)
+
+    for kind, seed, m, n in calls:
+        g, J, hist = run(b, kind, seed, m, n)
+        f = make()
+        g2, J2, hist2 = run(f, kind, seed, m, n)
+        iod.iod_batch_destroy(f)
+        assert np.array_equal(g, g2) and np.array_equal(J, J2), (kind, seed, m, n)
+        assert np.array_equal(hist, hist2), (kind, seed, m, n)
+    # the batch's evaluation without a wait in between: two sizes in a row on one stream
+    import torch
+    for m in ([300, 200, 100], [64, 64, 64]):
+        mm = np.array(m, dtype=np.int64)
+        off = iod.iod_batch_offsets(b, mm)
+        ld = int(off[-1])
+        xs = [W.random_swarm(11 + p, m[p], wls[p].lo, wls[p].hi) for p in range(3)]
+        x = torch.zeros((6, ld), dtype=torch.float64, device="cuda")
+        for p in range(3):
+            x[:, off[p]:off[p] + m[p]] = torch.from_numpy(np.ascontiguousarray(xs[p].T)).cuda()
+        c = torch.full((ld,), -1.0, dtype=torch.float64, device="cuda")
+        iod.iod_batch_eval(b, x, mm, c)
+        torch.cuda.synchronize()
+        got = c.cpu().numpy()
+        for p in range(3):
+            P = oracle.Problem(wls[p].mu, wls[p].h, wls[p].sigma, wls[p].chief, wls[p].t, obs[p])
+            want = oracle.cost(P, xs[p])
+            rel = np.abs(got[off[p]:off[p] + m[p]] - want) / np.abs(want)
+            assert rel.max() <= 1e-11, (m, p, rel.max())
+
+
+def test_repeated_polished_solves_match_fresh_batch(torch_dev):
+    wls = [W.tiny(s, K=6, T=0.6) for s in (1, 2)]
+    obs = [_obs(wl) for wl in wls]
+
+    def make():
+        return iod.iod_create_batch([wl.mu for wl in wls], [wl.chief for wl in wls],
+                                    [wl.t for wl in wls], obs, [wl.sigma for wl in wls],
+                                    h=wls[0].h)
+    params = [iod.pso_params(0.7, 1.5, 1.5, 2, wl.lo, wl.hi, problem=p)
+              for p, wl in enumerate(wls)]
+    m = np.array([256, 128], dtype=np.int64)
+    b = make()
+    outs = [iod.iod_batch_solve_polished(b, params, m, 5, top_k=16, n_cand=nc, n_gn=ng)
+            for nc, ng in ((8, 6), (4, 3), (8, 6))]
+    f = make()
+    fresh = iod.iod_batch_solve_polished(f, params, m, 5, top_k=16, n_cand=8, n_gn=6)
+    for a, c in zip(outs[0], outs[2]):
+        assert np.array_equal(a, c)
+    for a, c in zip(outs[0], fresh):
+        assert np.array_equal(a, c)
