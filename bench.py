@@ -9,7 +9,10 @@ update, global-best reduction) and the final global-best read-back. Inputs
 angles are the library's own prediction for the true deputy plus noise.
 
 Prints one JSON line. ``value`` is particle-RK4-steps/s of whole solves with
-inputs resident in HBM. ``roofline`` covers the dominant kernel (the fused
+inputs resident in HBM. The default run adds the batched half of the metric
+under ``c2`` (1,024 uneven problems, FP64), ``c3`` (the same batch in mixed
+precision) and ``c4`` (4,096 problems, mixed swarm + Gauss-Newton refinement,
+against the FP64 swarm + the same refinement at equal final error). ``roofline`` covers the dominant kernel (the fused
 iteration kernel): algorithmic FP64 flop-equivalents per launch divided by
 its average launch time, measured with HIP events on the launch stream.
 ``cpu_baseline`` times the reference oracle on a bounded sample of the same
@@ -427,6 +430,99 @@ def run_batch(args, iod, torch, top_k=0):
     }
 
 
+def batched_legs(iod, torch):
+    """The batched half of the metric, for the default run: one timed solve
+    each of the uneven batch in FP64 (1,024 problems x 150 iterations) and
+    in mixed precision (FP32 ranking + FP64 top-64), and of the refinement
+    workload (4,096 problems: mixed swarm of 100 iterations + Gauss-Newton on
+    16 candidates) against the FP64 swarm + the same refinement, whose final
+    states it must reach within 1e-9. Launch configurations come from a
+    short autotuner pass (3 iterations per candidate) on each batch."""
+    from paper_2207_13175_amd import workloads as W
+    out = {}
+    q = lambda a: [float(np.quantile(a, v)) for v in (0.1, 0.5, 0.9)]
+
+    wl = W.c2(0, screen=gpu_screen(iod, torch, W.MU_EARTH_MOON, 1e-3, 3.1))
+    b = batch_with_observations(iod, wl)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+              for p in range(wl.P)]
+    steps = iod.iod_batch_steps(b)
+    ps = int(wl.n_iter) * int(np.sum(wl.m * steps))
+    flop_iter = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
+    for key, top_k in (("c2", 0), ("c3", 64)):
+        cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
+        t0 = time.perf_counter()
+        if top_k:
+            g, J, _ = iod.iod_batch_solve_mixed(b, params, wl.m, wl.n_iter, top_k=top_k,
+                                                history=False)
+        else:
+            g, J, _ = iod.iod_batch_solve(b, params, wl.m, wl.n_iter, history=False)
+        el = time.perf_counter() - t0
+        it_ms = iod.iod_batch_last_iter_ms(b)
+        tf = flop_iter / (it_ms * 1e-3) / 1e12
+        err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
+        out[key] = {
+            "workload": wl.name + (f"_mixed_top{top_k}" if top_k else ""),
+            "dtype": "f32+f64" if top_k else "f64",
+            "problems": wl.P, "particles": int(wl.m.sum()), "iterations": wl.n_iter,
+            "problem_solves_per_s": wl.P / el, "particle_steps_per_s": ps / el,
+            "ms_per_solve": el * 1e3,
+            # one batched iteration: k_swarm_iter (FP64), or k_mixed_iter + k_topk +
+            # k_reeval64 (mixed), HIP events on the solve's stream
+            "ms_per_iter": it_ms,
+            "algorithmic_tflops": tf,
+            **({"frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
+                "frac_of_fp32_unpacked_peak": tf / PEAK_FP64_TFLOPS} if top_k
+               else {"frac_of_fp64_peak": tf / PEAK_FP64_TFLOPS}),
+            "pos_err_q10_50_90_lu": q(err),
+            "finite_costs": int(np.sum(np.isfinite(J))),
+            "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
+                          "waves": cfg.waves}}
+        print(f"# {key}: {wl.P / el:.1f} problem solves/s, {it_ms:.2f} ms per iteration",
+              file=sys.stderr, flush=True)
+    iod.iod_batch_destroy(b)
+
+    wl = W.c4(0, screen=gpu_screen(iod, torch, W.MU_EARTH_MOON, 1e-3, 2.6))
+    b = batch_with_observations(iod, wl)
+    params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+              for p in range(wl.P)]
+    cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
+    t0 = time.perf_counter()
+    g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
+                                              n_gn=20)
+    el = time.perf_counter() - t0
+    mixed_iter_ms = iod.iod_batch_last_iter_ms(b)
+    t0 = time.perf_counter()
+    g64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
+                                                 n_gn=20)
+    el64 = time.perf_counter() - t0
+    iod.iod_batch_destroy(b)
+    dpol = np.max(np.abs(g - g64), axis=1)
+    err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
+    e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
+    out["c4"] = {
+        "workload": wl.name + "_mixed_top64_refine16x20", "dtype": "f32+f64",
+        "problems": wl.P, "particles": int(wl.m.sum()), "iterations": wl.n_iter,
+        "problem_solves_per_s": wl.P / el, "ms_per_solve": el * 1e3,
+        "mixed_ms_per_iter": mixed_iter_ms,
+        "pos_err_q10_50_90_lu": q(err),
+        # the same refinement after a plain FP64 swarm of the same length: both
+        # routes end at the same least-squares minima (the precision gate below),
+        # so this is the speedup at equal final position error
+        "fp64_route_problem_solves_per_s": wl.P / el64,
+        "fp64_route_pos_err_q10_50_90_lu": q(e64),
+        "speedup_vs_fp64_route_at_equal_error": el64 / el,
+        "refined_state_diff_vs_fp64_route_q50_90_max": [float(np.quantile(dpol, 0.5)),
+                                                        float(np.quantile(dpol, 0.9)),
+                                                        float(np.max(dpol))],
+        "refined_within_1e-9_of_fp64_route": int(np.sum(dpol <= 1e-9)),
+        "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
+                      "waves": cfg.waves}}
+    print(f"# c4: {wl.P / el:.1f} problem solves/s; {int(np.sum(dpol <= 1e-9))} of {wl.P} "
+          f"within 1e-9 of the FP64 route", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,6 +538,8 @@ def main():
                     help="one of the paper's variants beside Algorithm 1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched legs (c2, c3, c4 keys) of the default run")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -575,6 +673,8 @@ def main():
     if args.variant == "none":
         # the FP32 half of the metric on the same problem and swarm
         out["fp32_eval"] = fp32_leg(iod, torch, wl, obs, sw.x, steps_per_eval)
+    if args.workload == "c1" and args.variant == "none" and not args.no_batched:
+        out.update(batched_legs(iod, torch))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, obs, args.cpu_seconds)
     print(json.dumps(out), flush=True)
