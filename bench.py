@@ -67,8 +67,9 @@ def load_counters():
     """From the committed rocprofv3 counter summary of the iteration kernel:
     calibrated HBM bytes per launch (FETCH_SIZE + WRITE_SIZE), FP64
     operations per evaluating launch ((2 FMA + MUL + ADD) x 64), VALU
-    instructions per wave per RK4 step and the clock during the launch; None
-    for all if the kernel sources changed since the counters were taken."""
+    quad-cycles per wave per RK4 step (SQ_ACTIVE_INST_VALU) and the clock
+    during the launch; None for all if the kernel sources changed since the
+    counters were taken."""
     none = (None, None, None, None)
     try:
         with open(TRAFFIC_FILE) as f:
@@ -79,19 +80,23 @@ def load_counters():
     if kv.get("kernel_sha") != kernel_hash():
         return none
     return (float(kv["hbm_bytes_per_launch"]), float(kv["total_64_ops_per_eval_launch"]),
-            float(kv["valu_per_wave_step"]), float(kv["clock_ghz"]))
+            float(kv["valu_quad_cycles_per_wave_step"]), float(kv["clock_ghz"]))
 
 
-def contract_ceiling(valu_per_step, clock_ghz, frac):
+def contract_ceiling(valu_quads_per_step, clock_ghz, frac):
     """The fraction of FP64 peak the arithmetic contract allows: one RK4 step
-    is FLOP_PER_STEP algorithmic flop-equivalents but valu_per_step issue
-    slots, which the peak counts as 2 flops each (FMA); at the measured
-    clock the ceiling scales by clock / 2.4 GHz."""
-    if valu_per_step is None:
+    is FLOP_PER_STEP algorithmic flop-equivalents per lane, which the peak
+    (16 FMA lanes per SIMD, 2 flops each) would issue in 64 FLOP_PER_STEP /
+    32 cycles per wave, but the step keeps the VALU busy for
+    valu_quads_per_step quad-cycles (correctly rounded sqrt and division for
+    bitwise parity; their transcendental seeds take four each). At the
+    measured clock the ceiling scales by clock / 2.4 GHz."""
+    if valu_quads_per_step is None:
         return None
-    at_peak_clock = FLOP_PER_STEP / (2.0 * valu_per_step)
+    at_peak_clock = FLOP_PER_STEP / (2.0 * valu_quads_per_step)
     at_clock = at_peak_clock * clock_ghz / PEAK_CLOCK_GHZ
-    return {"valu_per_wave_step": valu_per_step, "frac_at_2.4GHz_full_issue": at_peak_clock,
+    return {"valu_quad_cycles_per_wave_step": valu_quads_per_step,
+            "frac_at_2.4GHz_full_busy": at_peak_clock,
             "clock_ghz_measured": clock_ghz, "frac_at_measured_clock": at_clock,
             "achieved_over_ceiling_at_measured_clock": frac / at_clock}
 

@@ -23,8 +23,9 @@ def test_counter_record_is_tied_to_the_kernel_sources():
     if sha == bench.kernel_hash():
         assert traffic > 0 and ops > 0 and valu > 0 and clock > 0
         c = bench.contract_ceiling(valu, clock, 0.29)
-        # 186 flop-eq per step over two flops per issue slot, scaled by the clock
-        assert abs(c["frac_at_2.4GHz_full_issue"] - 186 / (2 * valu)) < 1e-12
-        assert c["frac_at_measured_clock"] < c["frac_at_2.4GHz_full_issue"] <= 1.0
+        # 186 flop-eq per lane-step against 4 cycles per VALU quad-cycle at
+        # 32 flops per SIMD cycle, scaled by the clock
+        assert abs(c["frac_at_2.4GHz_full_busy"] - 186 * 64 / 32 / (4 * valu)) < 1e-12
+        assert c["frac_at_measured_clock"] <= c["frac_at_2.4GHz_full_busy"] <= 1.0
     else:
         assert traffic is None and ops is None and valu is None and clock is None
