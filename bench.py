@@ -150,10 +150,21 @@ def observed_angles(iod, torch, wl, with_ranges=False):
 
 
 def fp32_leg(iod, torch, wl, obs, x, steps_per_eval, reps=5):
-    """The same problem as a one-problem batch: FP32 (Kahan) and FP64
-    evaluations of the swarm x [6, ld] (outside the timed solve), timed with
-    HIP events on the current stream; the FP32 costs' error against FP64."""
+    """The same problem as a one-problem batch: FP32 (Kahan) evaluations of
+    the swarm x [6, ld] in both FP32 formulations (the offset from the chief,
+    the default, and the absolute state) and the FP64 evaluation (outside the
+    timed solve), timed with HIP events on the current stream; the FP32
+    costs' error against FP64."""
+    out = {}
+    for key, mode in (("offset_formulation", iod.IOD_FP32_RELATIVE),
+                      ("absolute_formulation", iod.IOD_FP32_ABSOLUTE)):
+        out[key] = fp32_leg_mode(iod, torch, wl, obs, x, steps_per_eval, mode, reps)
+    return out
+
+
+def fp32_leg_mode(iod, torch, wl, obs, x, steps_per_eval, mode, reps):
     b = iod.iod_create_batch([wl.mu], [wl.chief], [wl.t], [obs], [wl.sigma], h=wl.h)
+    iod.iod_batch_set_fp32_mode(b, mode)
     m = np.array([wl.m], dtype=np.int64)
     ld = x.shape[1]
     c32 = torch.empty(ld, dtype=torch.float64, device="cuda")
@@ -252,6 +263,10 @@ def batch_with_observations(iod, wl, ranges=False):
                                 obs_ranges=rg, sigma_range=[W.SIGMA_RANGE] * wl.P)
 
 
+def fp32_mode_of(args, iod):
+    return iod.IOD_FP32_ABSOLUTE if args.fp32_mode == "absolute" else iod.IOD_FP32_RELATIVE
+
+
 def run_refine(args, iod, torch):
     """Refinement workload: mixed-precision swarm (2,048 particles, 100
     iterations, FP64 re-evaluation of the top 64) then Gauss-Newton on each
@@ -262,6 +277,7 @@ def run_refine(args, iod, torch):
     if args.iters is not None:
         wl.n_iter = args.iters
     b = batch_with_observations(iod, wl)
+    iod.iod_batch_set_fp32_mode(b, fp32_mode_of(args, iod))
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
               for p in range(wl.P)]
     cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
@@ -303,6 +319,7 @@ def run_refine(args, iod, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name + f"_mixed_top64_refine{n_cand}x{n_gn}", "problems": wl.P,
+                   "fp32_formulation": args.fp32_mode,
                    "particles": int(wl.m.sum()), "iterations": wl.n_iter,
                    "steps_range": [int(steps.min()), int(steps.max())],
                    "particle_steps_per_solve": ps,
@@ -347,6 +364,7 @@ def run_batch(args, iod, torch, top_k=0):
     if args.iters is not None:
         wl.n_iter = args.iters
     b = batch_with_observations(iod, wl, ranges=args.variant == "range")
+    iod.iod_batch_set_fp32_mode(b, fp32_mode_of(args, iod))
     vk = variant_params(args.variant, iod, wl)
     params = [iod.pso_params(vk["omega"], vk["eta1"], vk["eta2"], wl.pso_seed, wl.lo[p], wl.hi[p],
                              problem=p, flags=vk["flags"], tol=vk["tol"], tol_lag=vk["tol_lag"])
@@ -411,6 +429,7 @@ def run_batch(args, iod, torch, top_k=0):
         "config": {"workload": wl.name + (f"_mixed_top{top_k}" if top_k else "")
                                + ("" if args.variant == "none" else "_" + args.variant),
                    "variant": args.variant,
+                   **({"fp32_formulation": args.fp32_mode} if top_k else {}),
                    "iterations_run_q10_50_90": [float(np.quantile(n_run, v)) for v in (0.1, 0.5, 0.9)],
                    "mixed_vs_fp64": compare, "problems": wl.P, "particles": int(wl.m.sum()),
                    "iterations": wl.n_iter, "obs_range": [int(wl.K.min()), int(wl.K.max())],
@@ -454,7 +473,10 @@ def batched_legs(iod, torch):
     steps = iod.iod_batch_steps(b)
     ps = int(wl.n_iter) * int(np.sum(wl.m * steps))
     flop_iter = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
-    for key, top_k in (("c2", 0), ("c3", 64)):
+    for key, top_k, mode in (("c2", 0, None), ("c3", 64, iod.IOD_FP32_RELATIVE),
+                             ("c3_absolute", 64, iod.IOD_FP32_ABSOLUTE)):
+        if mode is not None:
+            iod.iod_batch_set_fp32_mode(b, mode)
         cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=top_k)
         t0 = time.perf_counter()
         if top_k:
@@ -469,6 +491,8 @@ def batched_legs(iod, torch):
         out[key] = {
             "workload": wl.name + (f"_mixed_top{top_k}" if top_k else ""),
             "dtype": "f32+f64" if top_k else "f64",
+            **({"fp32_formulation": "offset from the chief" if mode == iod.IOD_FP32_RELATIVE
+                else "absolute state"} if top_k else {}),
             "problems": wl.P, "particles": int(wl.m.sum()), "iterations": wl.n_iter,
             "problem_solves_per_s": wl.P / el, "particle_steps_per_s": ps / el,
             "ms_per_solve": el * 1e3,
@@ -485,28 +509,37 @@ def batched_legs(iod, torch):
                           "waves": cfg.waves}}
         print(f"# {key}: {wl.P / el:.1f} problem solves/s, {it_ms:.2f} ms per iteration",
               file=sys.stderr, flush=True)
+    out["c3"]["absolute_formulation"] = out.pop("c3_absolute")
     iod.iod_batch_destroy(b)
 
     wl = W.c4(0, screen=gpu_screen(iod, torch, W.MU_EARTH_MOON, 1e-3, 2.6))
     b = batch_with_observations(iod, wl)
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
               for p in range(wl.P)]
-    cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
-    t0 = time.perf_counter()
-    g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
-                                              n_gn=20)
-    el = time.perf_counter() - t0
-    mixed_iter_ms = iod.iod_batch_last_iter_ms(b)
+    # the refinement sets the final accuracy, so the swarm ranks with the faster
+    # absolute-state FP32 formulation; the offset formulation is timed beside it
+    runs = {}
+    for mode in (iod.IOD_FP32_ABSOLUTE, iod.IOD_FP32_RELATIVE):
+        iod.iod_batch_set_fp32_mode(b, mode)
+        cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
+        t0 = time.perf_counter()
+        g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64,
+                                                  n_cand=16, n_gn=20)
+        runs[mode] = (g, time.perf_counter() - t0, iod.iod_batch_last_iter_ms(b), cfg)
+    g, el, mixed_iter_ms, cfg = runs[iod.IOD_FP32_ABSOLUTE]
+    g_rel, el_rel, rel_iter_ms, _ = runs[iod.IOD_FP32_RELATIVE]
     t0 = time.perf_counter()
     g64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
                                                  n_gn=20)
     el64 = time.perf_counter() - t0
     iod.iod_batch_destroy(b)
     dpol = np.max(np.abs(g - g64), axis=1)
+    dpol_rel = np.max(np.abs(g_rel - g64), axis=1)
     err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
     e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
     out["c4"] = {
         "workload": wl.name + "_mixed_top64_refine16x20", "dtype": "f32+f64",
+        "fp32_formulation": "absolute state",
         "problems": wl.P, "particles": int(wl.m.sum()), "iterations": wl.n_iter,
         "problem_solves_per_s": wl.P / el, "ms_per_solve": el * 1e3,
         "mixed_ms_per_iter": mixed_iter_ms,
@@ -522,7 +555,13 @@ def batched_legs(iod, torch):
                                                         float(np.max(dpol))],
         "refined_within_1e-9_of_fp64_route": int(np.sum(dpol <= 1e-9)),
         "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
-                      "waves": cfg.waves}}
+                      "waves": cfg.waves},
+        "offset_formulation": {
+            "problem_solves_per_s": wl.P / el_rel, "ms_per_solve": el_rel * 1e3,
+            "mixed_ms_per_iter": rel_iter_ms,
+            "pos_err_q10_50_90_lu": q(np.linalg.norm(g_rel[:, :3] - wl.truth[:, :3], axis=1)),
+            "speedup_vs_fp64_route_at_equal_error": el64 / el_rel,
+            "refined_within_1e-9_of_fp64_route": int(np.sum(dpol_rel <= 1e-9))}}
     print(f"# c4: {wl.P / el:.1f} problem solves/s; {int(np.sum(dpol <= 1e-9))} of {wl.P} "
           f"within 1e-9 of the FP64 route", file=sys.stderr, flush=True)
     return out
@@ -541,6 +580,9 @@ def main():
                     help="personal bests refined per problem in the refinement workload")
     ap.add_argument("--variant", default="none", choices=VARIANTS,
                     help="one of the paper's variants beside Algorithm 1")
+    ap.add_argument("--fp32-mode", choices=("offset", "absolute"), default="offset",
+                    help="FP32 formulation of the mixed-precision workloads (c3, c4): the "
+                         "offset from the chief (default) or the absolute state")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",

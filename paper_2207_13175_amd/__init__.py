@@ -111,6 +111,8 @@ _SIGNATURES = {
                                      C.c_int32, C.POINTER(iod_launch_config), _D,
                                      C.POINTER(C.c_int32)]),
     "iod_batch_last_iter_ms": (C.c_double, [C.c_void_p]),
+    "iod_set_fp32_mode": (C.c_int, [C.c_void_p, C.c_int32]),
+    "iod_batch_set_fp32_mode": (C.c_int, [C.c_void_p, C.c_int32]),
     "iod_propagate_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "iod_batch_eval_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_void_p, C.c_void_p]),
     "iod_batch_select_topk": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _I64, C.c_int32,
@@ -511,6 +513,18 @@ def iod_batch_last_iter_ms(batch: Batch) -> float:
 # ----------------------------------------------------------------------------
 # Mixed precision
 # ----------------------------------------------------------------------------
+
+IOD_FP32_RELATIVE = 0
+IOD_FP32_ABSOLUTE = 1
+
+
+def iod_set_fp32_mode(handle: Handle, mode):
+    _check(lib().iod_set_fp32_mode(handle.ptr, int(mode)))
+
+
+def iod_batch_set_fp32_mode(batch: Batch, mode):
+    _check(lib().iod_batch_set_fp32_mode(batch.ptr, int(mode)))
+
 
 def iod_propagate_f32(handle: Handle, x, m, states, stream=None):
     """FP32 (Kahan) propagation; x: [6, ld] -> states: [K, 6, ld] (FP64 values)."""

@@ -164,9 +164,27 @@ int make_problem(double mu, const double *chief, const double *t, const double *
     return IOD_OK;
 }
 
-KArgs kargs_of(const HostProblem &P, const double *d_tab, const int32_t *d_ns)
+// Chief data of the FP32 propagation of one problem, in the tables of its
+// handle or batch (null until built).
+struct ChiefTables {
+    const float *cst = nullptr, *cpt = nullptr;
+    const double *cobs = nullptr;
+};
+
+// Sizes of a problem's chief tables: floats of the per-step rows (padded by
+// CST_CHUNK steps), floats of the per-observation partial-step rows, doubles
+// of the states at t = 0 and at the observations.
+int64_t cst_floats(const HostProblem &P) { return ((int64_t)P.ns[P.K - 1] + CST_CHUNK) * CST_STEP; }
+int64_t cpt_floats(const HostProblem &P) { return (int64_t)P.K * CST_STEP; }
+int64_t cobs_doubles(const HostProblem &P) { return ((int64_t)P.K + 1) * 6; }
+
+KArgs kargs_of(const HostProblem &P, const double *d_tab, const int32_t *d_ns,
+               const ChiefTables &T = ChiefTables())
 {
     KArgs A;
+    A.cst = T.cst;
+    A.cpt = T.cpt;
+    A.cobs = T.cobs;
     A.tab = d_tab;
     A.ns = d_ns;
     A.K = P.K;
@@ -454,8 +472,22 @@ struct iod_handle {
     hipStream_t stream = nullptr;
     DevCache solve_buf;
     GraphCache graphs;
+    // FP32 formulation, and the chief data of the offset formulation, built
+    // on its first call
+    int32_t fp32_mode = IOD_FP32_RELATIVE;
+    DevCache cst, cpt, cobs;
+    bool chief_built = false;
 
-    KArgs kargs() const { return kargs_of(P, d_tab, d_ns); }
+    KArgs kargs() const
+    {
+        ChiefTables T;
+        if (chief_built) {
+            T.cst = cst.as<const float>();
+            T.cpt = cpt.as<const float>();
+            T.cobs = cobs.as<const double>();
+        }
+        return kargs_of(P, d_tab, d_ns, T);
+    }
 };
 
 // Buffers of the batched refinement stage, kept across calls.
@@ -484,10 +516,22 @@ struct iod_batch {
     GraphCache graphs;
     DevTable eval_desc, eval_work, topk_desc, bpol_desc, bpol_work;
     PolishBuffers pol;
+    // FP32 formulation, and the chief data of the offset formulation, built
+    // on its first call: per-problem offsets into the three tables
+    int32_t fp32_mode = IOD_FP32_RELATIVE;
+    DevCache cst, cpt, cobs;
+    std::vector<int64_t> cst_off, cpt_off, cobs_off;
+    bool chief_built = false;
 
     KArgs kargs(int32_t p) const
     {
-        return kargs_of(probs[p], d_tab + tab_off[p] * TAB_W, d_ns + tab_off[p]);
+        ChiefTables T;
+        if (chief_built) {
+            T.cst = cst.as<const float>() + cst_off[p];
+            T.cpt = cpt.as<const float>() + cpt_off[p];
+            T.cobs = cobs.as<const double>() + cobs_off[p];
+        }
+        return kargs_of(probs[p], d_tab + tab_off[p] * TAB_W, d_ns + tab_off[p], T);
     }
 };
 
@@ -505,6 +549,59 @@ int check_batch(iod_batch *b)
     if (!b) return fail(IOD_EINVAL, "null batch");
     HIP_TRY(hipSetDevice(b->device));
     return IOD_OK;
+}
+
+// Build the chief data of the FP32 propagation (once per handle or batch):
+// allocate the three tables, then one thread per problem propagates its
+// chief in FP64 and fills them. Synchronous.
+int build_chief_tables(const std::vector<ProbDesc> &descs)
+{
+    DevBuf d;
+    HIP_TRY(hipMalloc(&d.p, descs.size() * sizeof(ProbDesc)));
+    HIP_TRY(hipMemcpy(d.p, descs.data(), descs.size() * sizeof(ProbDesc), hipMemcpyHostToDevice));
+    HIP_TRY(launch_chief_stages((const ProbDesc *)d.p, (int64_t)descs.size(), nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return IOD_OK;
+}
+
+int ensure_chief_tables(iod_handle *h)
+{
+    if (h->chief_built) return IOD_OK;
+    Phase ph("libiod: chief tables of the FP32 propagation");
+    HIP_TRY(h->cst.ensure((size_t)cst_floats(h->P) * sizeof(float)));
+    HIP_TRY(h->cpt.ensure((size_t)cpt_floats(h->P) * sizeof(float)));
+    HIP_TRY(h->cobs.ensure((size_t)cobs_doubles(h->P) * sizeof(double)));
+    h->chief_built = true;
+    int rc = build_chief_tables({desc_of(h->kargs(), h->P.chief, nullptr)});
+    if (rc != IOD_OK) h->chief_built = false;
+    return rc;
+}
+
+int ensure_chief_tables(iod_batch *b)
+{
+    if (b->chief_built) return IOD_OK;
+    Phase ph("libiod: chief tables of the FP32 propagation");
+    b->cst_off.assign(b->P, 0);
+    b->cpt_off.assign(b->P, 0);
+    b->cobs_off.assign(b->P, 0);
+    int64_t ncst = 0, ncpt = 0, ncobs = 0;
+    for (int32_t p = 0; p < b->P; ++p) {
+        b->cst_off[p] = ncst;
+        b->cpt_off[p] = ncpt;
+        b->cobs_off[p] = ncobs;
+        ncst += cst_floats(b->probs[p]);
+        ncpt += cpt_floats(b->probs[p]);
+        ncobs += cobs_doubles(b->probs[p]);
+    }
+    HIP_TRY(b->cst.ensure((size_t)ncst * sizeof(float)));
+    HIP_TRY(b->cpt.ensure((size_t)ncpt * sizeof(float)));
+    HIP_TRY(b->cobs.ensure((size_t)ncobs * sizeof(double)));
+    b->chief_built = true;
+    std::vector<ProbDesc> descs(b->P);
+    for (int32_t p = 0; p < b->P; ++p) descs[p] = desc_of(b->kargs(p), b->probs[p].chief, nullptr);
+    int rc = build_chief_tables(descs);
+    if (rc != IOD_OK) b->chief_built = false;
+    return rc;
 }
 
 int check_swarm_view(const double *x, int64_t ld, int64_t m, const void *out)
@@ -679,6 +776,15 @@ int iod_get_config(const iod_handle *h, iod_launch_config *cfg)
 {
     if (!h || !cfg) return fail(IOD_EINVAL, "null pointer");
     *cfg = h->cfg;
+    return IOD_OK;
+}
+
+int iod_set_fp32_mode(iod_handle *h, int32_t mode)
+{
+    if (!h) return fail(IOD_EINVAL, "null handle");
+    if (mode != IOD_FP32_RELATIVE && mode != IOD_FP32_ABSOLUTE)
+        return fail(IOD_EINVAL, "unknown FP32 mode %d", mode);
+    h->fp32_mode = mode;
     return IOD_OK;
 }
 
@@ -995,6 +1101,15 @@ int iod_batch_get_config(const iod_batch *b, iod_launch_config *cfg)
     return IOD_OK;
 }
 
+int iod_batch_set_fp32_mode(iod_batch *b, int32_t mode)
+{
+    if (!b) return fail(IOD_EINVAL, "null batch");
+    if (mode != IOD_FP32_RELATIVE && mode != IOD_FP32_ABSOLUTE)
+        return fail(IOD_EINVAL, "unknown FP32 mode %d", mode);
+    b->fp32_mode = mode;
+    return IOD_OK;
+}
+
 int64_t iod_batch_offsets(const iod_batch *b, const int64_t *m, int64_t *off)
 {
     if (!b || !m || !off) return fail(IOD_EINVAL, "null pointer");
@@ -1077,8 +1192,11 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
               const PolishStage *stage = nullptr)
 {
     const int bs = block_of(cfg);
+    const bool rel = top_k > 0 && b->fp32_mode == IOD_FP32_RELATIVE;
+    int rc = rel ? ensure_chief_tables(b) : IOD_OK;
+    if (rc != IOD_OK) return rc;
     BatchLayout L;
-    int rc = batch_layout(b, params, m, bs, cfg.order, L);
+    rc = batch_layout(b, params, m, bs, cfg.order, L);
     if (rc != IOD_OK) return rc;
     Phase swarm_phase(top_k ? "iod_batch: mixed-precision swarm" : "iod_batch: FP64 swarm");
     const int64_t P = b->P, ld = L.ld;
@@ -1118,7 +1236,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     // one iteration: FP64 fused launch, or FP32 launch + top-k + FP64 re-evaluation
     auto iterate = [&](int64_t n) -> hipError_t {
         if (top_k == 0) return launch_swarm_iter(d0, B, bs, L.grid, n, st, cfg.waves);
-        hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, st);
+        hipError_t e = launch_mixed_iter(d0, B, bs, L.grid, n, rel, st);
         if (e == hipSuccess) e = launch_topk(B, B.jp, top_k, cand, st);
         if (e == hipSuccess) e = launch_reeval64(B, cand, top_k, n, st);
         return e;
@@ -1126,7 +1244,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     if (top_k == 0) {
         HIP_TRY(launch_swarm_init(d0, B, bs, L.grid, st));
     } else {
-        HIP_TRY(launch_mixed_init(d0, B, bs, L.grid, st));
+        HIP_TRY(launch_mixed_init(d0, B, bs, L.grid, rel, st));
         HIP_TRY(launch_topk(B, B.jp, top_k, cand, st));
         HIP_TRY(launch_reeval64(B, cand, top_k, 0, st));
     }
@@ -1142,7 +1260,7 @@ int batch_run(iod_batch *b, const iod_pso_params *params, const int64_t *m, int6
     // from device tables (refreshed above when they change); the key holds
     // every launch argument
     Key key;
-    key.add(d0).add(B).add(bs).add(L.grid).add(cfg.waves).add(top_k).add(cand);
+    key.add(d0).add(B).add(bs).add(L.grid).add(cfg.waves).add(top_k).add(cand).add(rel);
     rc = run_iterations(st, cfg.graph != 0, n0, n_iter - n0, iterate, &b->graphs, key);
     if (rc == IOD_OK && iter_ms) {
         hipError_t e = hipEventRecord(b->ev1, st);
@@ -1224,7 +1342,10 @@ int iod_propagate_f32(iod_handle *h, const double *x, int64_t ld, int64_t m, dou
     int rc = check_handle(h);
     if (rc == IOD_OK) rc = check_swarm_view(x, ld, m, states);
     if (rc != IOD_OK || m == 0) return rc;
-    HIP_TRY(launch_propagate32(h->kargs(), x, ld, m, states, (hipStream_t)stream));
+    const bool rel = h->fp32_mode == IOD_FP32_RELATIVE;
+    if (rel) rc = ensure_chief_tables(h);
+    if (rc != IOD_OK) return rc;
+    HIP_TRY(launch_propagate32(h->kargs(), x, ld, m, states, rel, (hipStream_t)stream));
     return IOD_OK;
 }
 
@@ -1282,6 +1403,13 @@ int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m,
     if (ld < L.ld) return fail(IOD_EINVAL, "ld = %lld < %lld", (long long)ld, (long long)L.ld);
     if (L.grid == 0) return IOD_OK;
     if (!x || !cost) return fail(IOD_EINVAL, "null device pointer");
+    const bool rel = b->fp32_mode == IOD_FP32_RELATIVE;
+    if (f32 && rel && !b->chief_built) {
+        rc = ensure_chief_tables(b);
+        if (rc != IOD_OK) return rc;
+        rc = batch_layout(b, nullptr, m, bs, b->cfg.order, L);
+        if (rc != IOD_OK) return rc;
+    }
     hipStream_t st = (hipStream_t)stream;
     // the launch tables are the batch's, copied only when they change, so the
     // call returns without waiting for the device
@@ -1297,7 +1425,7 @@ int batch_eval_impl(iod_batch *b, const double *x, int64_t ld, const int64_t *m,
     B.nprob = b->P;
     B.total_slots = L.total_slots;
     if (f32)
-        HIP_TRY(launch_eval32(L.descs[0], B, bs, L.grid, st));
+        HIP_TRY(launch_eval32(L.descs[0], B, bs, L.grid, rel, st));
     else
         HIP_TRY(launch_eval(L.descs[0], B, bs, L.grid, st));
     return IOD_OK;

@@ -23,6 +23,18 @@ constexpr int OBS_CHUNK = 64;
 // Global-best record and argmin slot: [key, index, state[6]].
 constexpr int REC = 8;
 
+// Chief data of the FP32 propagation, which integrates the deputy's offset
+// from the chief: for each of the four stage inputs C of a chief RK4 step
+// (FP64, the integrator's own order), CST_W floats
+//   d1x = Cx + mu, d2x = Cx - (1 - mu), Cy, Cz,
+//   1/|d1|^2, 1/|d2|^2, (1 - mu)/|d1|^3, mu/|d2|^3,
+// with d_j the chief's offset from primary j.
+constexpr int CST_W = 8;
+constexpr int CST_STEP = 4 * CST_W;   // floats per RK4 step
+// Steps of chief data staged in LDS at a time; the per-step table carries
+// this many zero rows past its last step, so a chunk never reads past it.
+constexpr int CST_CHUNK = 16;
+
 // Dynamics, observation table and cost of one problem.
 struct KArgs {
     const double *tab;  // device [K][TAB_W]
@@ -34,6 +46,10 @@ struct KArgs {
     double h, h2, h6;   // h, h/2, h/6
     double w;           // 1 / sigma^2
     double wr;          // 1 / sigma_range^2, 0 = angles only
+    // chief data of the FP32 propagation (null until an FP32 call needs it)
+    const float *cst;   // device [ns[K-1] + CST_CHUNK][CST_STEP]: every grid step
+    const float *cpt;   // device [K][CST_STEP]: each observation's partial step (if any)
+    const double *cobs; // device [K + 1][6]: the chief state at t = 0, then at each observation
 };
 
 // Swarm variants (bits of ProbDesc::flags; the values of iod.h's IOD_PSO_*).

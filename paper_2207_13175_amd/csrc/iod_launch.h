@@ -32,15 +32,20 @@ hipError_t launch_swarm_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, i
                              int64_t n, hipStream_t st, int waves = 0);
 hipError_t launch_swarm_final(const ProbDesc &d0, const SwarmArrays &B, int64_t n, hipStream_t st);
 
+// Chief data of the FP32 propagation for each problem (one thread each):
+// fills the cst, cpt and cobs tables that descs[p].k points to.
+hipError_t launch_chief_stages(const ProbDesc *descs, int64_t nprob, hipStream_t st);
 // Mixed precision (FP32 ranking, FP64 global best); batched launches only.
+// rel: the offset-from-the-chief formulation (the problems' chief tables
+// must be built); else the absolute-state formulation.
 hipError_t launch_propagate32(const KArgs &A, const double *x, int64_t ld, int64_t m,
-                              double *states, hipStream_t st);
+                              double *states, bool rel, hipStream_t st);
 hipError_t launch_eval32(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                         hipStream_t st);
+                         bool rel, hipStream_t st);
 hipError_t launch_mixed_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             hipStream_t st);
+                             bool rel, hipStream_t st);
 hipError_t launch_mixed_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             int64_t n, hipStream_t st);
+                             int64_t n, bool rel, hipStream_t st);
 // out: device [nprob][top_k] particle indices (-1 past m), top_k <= TOPK_MAX.
 hipError_t launch_topk(const SwarmArrays &B, const double *keys, int32_t top_k, int32_t *out,
                        hipStream_t st);

@@ -1,23 +1,111 @@
 // iod_mixed.hip -- gfx950 kernels of libiod's mixed-precision swarm: FP32
-// RK4 propagation with a Kahan-compensated state ranks the particles; per
-// problem the top-k personal bests are selected and re-evaluated in FP64,
-// and the global best of Algorithm 1 (Zuehlke et al., AAS 22-770) is decided
-// on those FP64 costs. A systems variant: the paper works in double
-// precision throughout.
+// RK4 propagation (of each particle's offset from the chief by default, or of
+// its absolute state) with Kahan-compensated accumulation ranks the
+// particles; per problem the top-k personal bests are selected and
+// re-evaluated in FP64, and the global best of Algorithm 1 (Zuehlke et al.,
+// AAS 22-770) is decided on those FP64 costs. A systems variant: the paper
+// works in double precision throughout.
 #include "iod_device.h"
 #include "iod_launch.h"
 
 namespace iodk {
 
 // ---------------------------------------------------------------------------
-// Mixed precision: FP32 propagation with a Kahan-compensated state, used to
-// rank particles; FP64 re-evaluation of the best candidates decides the
-// global best.
+// Mixed precision: FP32 propagation of each particle's offset from the chief
+// (Encke's formulation), with Kahan-compensated accumulation, used to rank
+// particles; FP64 re-evaluation of the best candidates decides the global
+// best.
+//
+// The deputy's state is the chief's FP64 RK4 state plus an offset delta.
+// delta follows the same RK4 map: each stage's derivative is the difference
+// of the equations of motion at chief + delta and at the chief's own stage
+// input. The linear terms (velocity, Coriolis, centrifugal) act on delta
+// directly; each primary's attraction contributes
+//   -mu_j [(d + delta) / b^3 - d / a^3] = -mu_j/a^3 [w^3 delta + (w^3 - 1) d],
+// with d the chief's offset from the primary, a = |d|, b = |d + delta|,
+// u = (b^2 - a^2) / a^2 = (2 d + delta) . delta / a^2, w = (1 + u)^-1/2, and
+//   w^3 - 1 = -u (3 + 3u + u^2) w^6 / (1 + w^3),
+// so nothing cancels: every rounding error is relative to the perturbation,
+// which is |delta| / |d| (1e-3 to 1e-2) of the attraction itself. The
+// chief-only factors (d, 1/a^2, mu_j/a^3) come per stage from a table the
+// chief kernel writes in FP64 and rounds to FP32. The residual at an
+// observation uses rho = delta itself: no deputy-chief cancellation either.
 // ---------------------------------------------------------------------------
+
+// Derivative of the offset s = (delta position, delta velocity) at one stage,
+// row = that stage's chief data (CST_W floats). 1/sqrt and 1/x are the
+// hardware FP32 estimates (about 1 ulp).
+__device__ __forceinline__ void rhs32_rel(const float *row, const float s[6], float f[6])
+{
+    const float d1x = row[0], d2x = row[1], cy = row[2], cz = row[3];
+    const float ia1 = row[4], ia2 = row[5], k1 = row[6], k2 = row[7];
+    const float dx = s[0], dy = s[1], dz = s[2];
+    const float syz = fmaf(fmaf(2.0f, cy, dy), dy, fmaf(2.0f, cz, dz) * dz);
+    const float u1 = fmaf(fmaf(2.0f, d1x, dx), dx, syz) * ia1;
+    const float u2 = fmaf(fmaf(2.0f, d2x, dx), dx, syz) * ia2;
+    const float w1 = __builtin_amdgcn_rsqf(1.0f + u1);
+    const float w2 = __builtin_amdgcn_rsqf(1.0f + u2);
+    const float w13 = w1 * w1 * w1, w23 = w2 * w2 * w2;
+    const float f1 = -(u1 * fmaf(u1, u1 + 3.0f, 3.0f) * (w13 * w13)) * __builtin_amdgcn_rcpf(1.0f + w13);
+    const float f2 = -(u2 * fmaf(u2, u2 + 3.0f, 3.0f) * (w23 * w23)) * __builtin_amdgcn_rcpf(1.0f + w23);
+    const float cs = fmaf(k1, w13, k2 * w23);
+    const float e1 = k1 * f1, e2 = k2 * f2;
+    const float es = e1 + e2;
+    f[0] = s[3];
+    f[1] = s[4];
+    f[2] = s[5];
+    f[3] = fmaf(2.0f, s[4], dx) - fmaf(cs, dx, fmaf(e1, d1x, e2 * d2x));
+    f[4] = fmaf(-2.0f, s[3], dy) - fmaf(cs, dy, es * cy);
+    f[5] = -fmaf(cs, dz, es * cz);
+}
+
+// One RK4 step of the offset (stages see D; the increment h/6 (k1 + 2k2 +
+// 2k3 + k4) is added with Kahan compensation, C holding minus the lost low
+// part, so the accumulated offset is D - C). rows: the step's four stage
+// rows of chief data.
+__device__ __forceinline__ void rk4_32_rel(const float *rows, float h, float h2, float h6,
+                                           float D[6], float C[6])
+{
+    float k[6], a[6], s[6];
+    rhs32_rel(rows, D, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = k[d];
+        s[d] = fmaf(h2, k[d], D[d]);
+    }
+    rhs32_rel(rows + CST_W, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fmaf(2.0f, k[d], a[d]);
+        s[d] = fmaf(h2, k[d], D[d]);
+    }
+    rhs32_rel(rows + 2 * CST_W, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fmaf(2.0f, k[d], a[d]);
+        s[d] = fmaf(h, k[d], D[d]);
+    }
+    rhs32_rel(rows + 3 * CST_W, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = a[d] + k[d];
+        const float yv = fmaf(h6, a[d], -C[d]);
+        const float t = D[d] + yv;
+        C[d] = (t - D[d]) - yv;
+        D[d] = t;
+    }
+}
+
+// The absolute formulation (IOD_FP32_ABSOLUTE): the deputy's own state in
+// FP32 with a Kahan-compensated accumulation. Fewer operations per stage,
+// but the rounding error of each derivative is relative to the whole
+// acceleration, not to the deputy-chief difference, and the residual
+// subtracts the chief position from the deputy's: position errors about 400
+// times larger than the offset formulation's on the workloads here.
 
 // FP32 right-hand side. 1/r^3 comes from the hardware reciprocal square root
 // (about 1 ulp), cubed: c_j = mu_j rsq(r_j^2)^3.
-__device__ __forceinline__ void rhs32(float mu, float mu1, const float s[6], float f[6])
+__device__ __forceinline__ void rhs32_abs(float mu, float mu1, const float s[6], float f[6])
 {
     const float x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4];
     const float d1 = x + mu;
@@ -36,32 +124,31 @@ __device__ __forceinline__ void rhs32(float mu, float mu1, const float s[6], flo
     f[5] = -(cs * z);
 }
 
-// FP32 RK4 step. The stages see X; the increment h/6 (k1 + 2k2 + 2k3 + k4)
-// is added with Kahan compensation, C holding minus the lost low part, so
-// the accumulated state is X - C.
-__device__ __forceinline__ void rk4_32(float mu, float mu1, float h, float h2, float h6,
-                                       float X[6], float C[6])
+// FP32 RK4 step of the state (stages see X; the increment is added with
+// Kahan compensation, the accumulated state being X - C).
+__device__ __forceinline__ void rk4_32_abs(float mu, float mu1, float h, float h2, float h6,
+                                           float X[6], float C[6])
 {
     float k[6], a[6], s[6];
-    rhs32(mu, mu1, X, k);
+    rhs32_abs(mu, mu1, X, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = k[d];
         s[d] = fmaf(h2, k[d], X[d]);
     }
-    rhs32(mu, mu1, s, k);
+    rhs32_abs(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fmaf(2.0f, k[d], a[d]);
         s[d] = fmaf(h2, k[d], X[d]);
     }
-    rhs32(mu, mu1, s, k);
+    rhs32_abs(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fmaf(2.0f, k[d], a[d]);
         s[d] = fmaf(h, k[d], X[d]);
     }
-    rhs32(mu, mu1, s, k);
+    rhs32_abs(mu, mu1, s, k);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = a[d] + k[d];
@@ -72,10 +159,11 @@ __device__ __forceinline__ void rk4_32(float mu, float mu1, float h, float h2, f
     }
 }
 
-// FP32 walk of the schedule; obs(row, X, C) sees the compensated pair.
+// FP32 walk of the schedule over the state; obs(row, k, X, C) sees the
+// compensated pair at observation k.
 template <class Obs>
-__device__ __forceinline__ void walk32(const KArgs &A, float X[6], float C[6], double *lds,
-                                       int32_t *lds_ns, Obs &obs)
+__device__ __forceinline__ void walk32_abs(const KArgs &A, float X[6], float C[6], double *lds,
+                                           int32_t *lds_ns, Obs &obs)
 {
     const float mu = (float)A.mu, mu1 = (float)A.mu1;
     const float h = (float)A.h, h2 = 0.5f * h, h6 = h / 6.0f;
@@ -90,7 +178,7 @@ __device__ __forceinline__ void walk32(const KArgs &A, float X[6], float C[6], d
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
             const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
-            for (; step < target; ++step) rk4_32(mu, mu1, h, h2, h6, X, C);
+            for (; step < target; ++step) rk4_32_abs(mu, mu1, h, h2, h6, X, C);
             const float tau = (float)row[TAB_TAU];
             float S[6], SC[6];
 #pragma unroll
@@ -98,29 +186,82 @@ __device__ __forceinline__ void walk32(const KArgs &A, float X[6], float C[6], d
                 S[d] = X[d];
                 SC[d] = C[d];
             }
-            if (tau != 0.0f) rk4_32(mu, mu1, tau, 0.5f * tau, tau / 6.0f, S, SC);
-            obs(row, S, SC);
+            if (tau != 0.0f) rk4_32_abs(mu, mu1, tau, 0.5f * tau, tau / 6.0f, S, SC);
+            obs(row, k0 + kk, S, SC);
         }
     }
 }
 
-// FP32 residual cost. rho = (X - C) - r_chief is formed as
-// (X - rc_hi) - (C + rc_lo) with the chief split into an FP32 pair, so the
-// small chief-to-deputy offset keeps the precision of the compensated state.
+// FP32 walk of the schedule over the offset from the chief (the default);
+// obs(row, k, D, C) sees the
+// compensated pair at observation k. The chief data of the grid steps is
+// staged through LDS (lds_c, CST_CHUNK steps) by the whole workgroup, whose
+// threads all follow one problem's schedule; a partial step reads its rows
+// from the observation's own table entry.
+template <class Obs>
+__device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6], double *lds,
+                                           int32_t *lds_ns, float *lds_c, Obs &obs)
+{
+    const float h = (float)A.h, h2 = 0.5f * h, h6 = h / 6.0f;
+    int32_t step = 0, c0 = -CST_CHUNK;
+    for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
+        const int32_t nk = min(OBS_CHUNK, A.K - k0);
+        __syncthreads();
+        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
+            lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
+        for (int32_t j = threadIdx.x; j < nk; j += blockDim.x) lds_ns[j] = A.ns[k0 + j];
+        __syncthreads();
+        for (int32_t kk = 0; kk < nk; ++kk) {
+            const double *row = lds + kk * TAB_W;
+            const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
+            for (; step < target; ++step) {
+                if (step >= c0 + CST_CHUNK) {
+                    c0 = step;
+                    __syncthreads();
+                    for (int32_t j = threadIdx.x; j < CST_CHUNK * CST_STEP; j += blockDim.x)
+                        lds_c[j] = A.cst[(int64_t)c0 * CST_STEP + j];
+                    __syncthreads();
+                }
+                rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, D, C);
+            }
+            const float tau = (float)row[TAB_TAU];
+            float S[6], SC[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                S[d] = D[d];
+                SC[d] = C[d];
+            }
+            if (tau != 0.0f)
+                rk4_32_rel(A.cpt + (int64_t)(k0 + kk) * CST_STEP, tau, 0.5f * tau, tau / 6.0f, S, SC);
+            obs(row, k0 + kk, S, SC);
+        }
+    }
+}
+
+// FP32 residual cost. REL: rho is the compensated offset S - C at the
+// observation (the deputy's offset from the chief is the line of sight).
+// Absolute: rho = (S - C) - r_chief is formed as (S - rc_hi) - (C + rc_lo),
+// with the FP64 chief position split into an FP32 pair.
+template <bool REL>
 struct CostAcc32 {
     double J;
     float w;
     int32_t mode;
     float wr;   // range weight, 0 = angles only
-    __device__ __forceinline__ void operator()(const double *row, const float S[6], const float C[6])
+    __device__ __forceinline__ void operator()(const double *row, int32_t, const float S[6],
+                                               const float C[6])
     {
         float r[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const double rc = row[TAB_RC + d];
-            const float hi = (float)rc;
-            const float lo = (float)(rc - (double)hi);
-            r[d] = (S[d] - hi) - (C[d] + lo);
+            if (REL) {
+                r[d] = S[d] - C[d];
+            } else {
+                const double rc = row[TAB_RC + d];
+                const float hi = (float)rc;
+                const float lo = (float)(rc - (double)hi);
+                r[d] = (S[d] - hi) - (C[d] + lo);
+            }
         }
         const float sa = (float)row[TAB_SA], ca = (float)row[TAB_CA];
         const float sb = (float)row[TAB_SB], cb = (float)row[TAB_CB];
@@ -150,78 +291,206 @@ struct CostAcc32 {
     }
 };
 
-__device__ __forceinline__ double eval_cost32(const KArgs &A, const double x0[6], double *lds,
-                                              int32_t *lds_ns)
+// The offset of x0 from the chief's initial state (row 0 of cobs) as an
+// FP32 pair: the FP64 difference is exact for nearby states, and D - C
+// carries it to ~2^-48 relative.
+__device__ __forceinline__ void offset32(const KArgs &A, const double x0[6], float D[6], float C[6])
 {
-    float X[6], C[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const double o = x0[d] - A.cobs[d];
+        D[d] = (float)o;
+        C[d] = -(float)(o - (double)D[d]);
+    }
+}
+
+// The absolute state as an FP32 pair: X - C carries x0 to ~2^-48.
+__device__ __forceinline__ void state32(const double x0[6], float X[6], float C[6])
+{
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         X[d] = (float)x0[d];
-        C[d] = -(float)(x0[d] - (double)X[d]);   // X - C carries x0 to ~2^-48
+        C[d] = -(float)(x0[d] - (double)X[d]);
     }
-    CostAcc32 acc{0.0, (float)A.w, A.mode, (float)A.wr};
-    walk32(A, X, C, lds, lds_ns, acc);
+}
+
+// Walk of either formulation: the offset from the chief (REL) or the state.
+template <bool REL, class Obs>
+__device__ __forceinline__ void walk32(const KArgs &A, const double x0[6], double *lds,
+                                       int32_t *lds_ns, float *lds_c, Obs &obs)
+{
+    float D[6], C[6];
+    if (REL) {
+        offset32(A, x0, D, C);
+        walk32_rel(A, D, C, lds, lds_ns, lds_c, obs);
+    } else {
+        state32(x0, D, C);
+        walk32_abs(A, D, C, lds, lds_ns, obs);
+    }
+}
+
+template <bool REL>
+__device__ __forceinline__ double eval_cost32(const KArgs &A, const double x0[6], double *lds,
+                                              int32_t *lds_ns, float *lds_c)
+{
+    CostAcc32<REL> acc{0.0, (float)A.w, A.mode, (float)A.wr};
+    walk32<REL>(A, x0, lds, lds_ns, lds_c, acc);
     return acc.J;
 }
 
+// States at the observations: the compensated pair, plus the chief's FP64
+// state in the offset formulation.
+template <bool REL>
 struct StoreStates32 {
+    const double *cobs;
     double *out;
     int64_t ld, i;
-    int32_t k;
     bool valid;
-    __device__ __forceinline__ void operator()(const double *, const float S[6], const float C[6])
+    __device__ __forceinline__ void operator()(const double *, int32_t k, const float S[6],
+                                               const float C[6])
     {
         if (valid) {
 #pragma unroll
             for (int d = 0; d < 6; ++d)
-                out[((int64_t)k * 6 + d) * ld + i] = (double)S[d] - (double)C[d];
+                out[((int64_t)k * 6 + d) * ld + i] =
+                    (REL ? cobs[(int64_t)(k + 1) * 6 + d] : 0.0) + ((double)S[d] - (double)C[d]);
         }
-        ++k;
     }
 };
 
+template <bool REL>
 __global__ __launch_bounds__(256) void k_propagate32(KArgs A, const double *__restrict__ x,
                                                      int64_t ld, int64_t m,
                                                      double *__restrict__ states)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
+    __shared__ float lds_c[REL ? CST_CHUNK * CST_STEP : 1];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < m;
     const int64_t j = valid ? i : m - 1;
-    float X[6], C[6];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        const double v = x[d * ld + j];
-        X[d] = (float)v;
-        C[d] = -(float)(v - (double)X[d]);
-    }
-    StoreStates32 obs{states, ld, i, 0, valid};
-    walk32(A, X, C, lds, lds_ns, obs);
+    double x0[6];
+    load_state(x, ld, j, x0);
+    StoreStates32<REL> obs{A.cobs, states, ld, i, valid};
+    walk32<REL>(A, x0, lds, lds_ns, lds_c, obs);
 }
 
-template <int BS>
+// The chief data of one problem (one thread each): the FP64 RK4 of the
+// chief in the integrator's own order (the IEEE path, so the same states as
+// every FP64 kernel), writing the stage rows of every grid step, the rows of
+// each off-grid observation's partial step, and the chief state at t = 0
+// and at every observation. Padding rows past the last step are zero.
+__device__ __forceinline__ void chief_row(double mu, double mu1, const double s[6], float *row)
+{
+    const double d1x = s[0] + mu;
+    const double d2x = s[0] - mu1;
+    const double q = fma(s[2], s[2], s[1] * s[1]);
+    const double a1s = fma(d1x, d1x, q);
+    const double a2s = fma(d2x, d2x, q);
+    row[0] = (float)d1x;
+    row[1] = (float)d2x;
+    row[2] = (float)s[1];
+    row[3] = (float)s[2];
+    row[4] = (float)(1.0 / a1s);
+    row[5] = (float)(1.0 / a2s);
+    row[6] = (float)(mu1 / (a1s * sqrt(a1s)));
+    row[7] = (float)(mu / (a2s * sqrt(a2s)));
+}
+
+__device__ __forceinline__ void chief_step_rows(double mu, double mu1, double h, double h2,
+                                                double h6, double X[6], float *rows)
+{
+    double k[6], s[6], a[6];
+    chief_row(mu, mu1, X, rows);
+    rhs<false>(mu, mu1, X, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = k[d];
+        s[d] = fma(h2, k[d], X[d]);
+    }
+    chief_row(mu, mu1, s, rows + CST_W);
+    rhs<false>(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s[d] = fma(h2, k[d], X[d]);
+    }
+    chief_row(mu, mu1, s, rows + 2 * CST_W);
+    rhs<false>(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        a[d] = fma(2.0, k[d], a[d]);
+        s[d] = fma(h, k[d], X[d]);
+    }
+    chief_row(mu, mu1, s, rows + 3 * CST_W);
+    rhs<false>(mu, mu1, s, k);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) a[d] = a[d] + k[d];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) X[d] = fma(h6, a[d], X[d]);
+}
+
+__global__ __launch_bounds__(64) void k_chief_stages(const ProbDesc *__restrict__ descs,
+                                                     int64_t nprob)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const ProbDesc &D = descs[p];
+    const KArgs &A = D.k;
+    float *cst = const_cast<float *>(A.cst);
+    float *cpt = const_cast<float *>(A.cpt);
+    double *cobs = const_cast<double *>(A.cobs);
+    double X[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        X[d] = D.chief[d];
+        cobs[d] = X[d];
+    }
+    int32_t step = 0;
+    for (int32_t k = 0; k < A.K; ++k) {
+        const int32_t target = A.ns[k];
+        for (; step < target; ++step)
+            chief_step_rows(A.mu, A.mu1, A.h, A.h2, A.h6, X, cst + (int64_t)step * CST_STEP);
+        const double tau = A.tab[(int64_t)k * TAB_W + TAB_TAU];
+        double S[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) S[d] = X[d];
+        float *prow = cpt + (int64_t)k * CST_STEP;
+        if (tau != 0.0) {
+            chief_step_rows(A.mu, A.mu1, tau, 0.5 * tau, tau / 6.0, S, prow);
+        } else {
+            for (int j = 0; j < CST_STEP; ++j) prow[j] = 0.0f;
+        }
+#pragma unroll
+        for (int d = 0; d < 6; ++d) cobs[(int64_t)(k + 1) * 6 + d] = S[d];
+    }
+    for (int32_t j = 0; j < CST_CHUNK * CST_STEP; ++j) cst[(int64_t)step * CST_STEP + j] = 0.0f;
+}
+
+template <int BS, bool REL>
 __global__ __launch_bounds__(BS) void k_eval32(ProbDesc d0, SwarmArrays B)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
+    __shared__ float lds_c[REL ? CST_CHUNK * CST_STEP : 1];
     int64_t p, tile;
     const ProbDesc &D = locate<false>(d0, B, p, tile);
     const int64_t i = tile * BS + threadIdx.x;
     const bool valid = i < D.m;
     double X[6];
     load_state(B.x, B.ld, D.off + (valid ? i : D.m - 1), X);
-    const double J = eval_cost32(D.k, X, lds, lds_ns);
+    const double J = eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c);
     if (valid) B.cost[D.off + i] = J;
 }
 
 // Mixed-precision initialisation: as k_swarm_init with FP32 ranking costs;
 // no argmin slots (the global best comes from the FP64 re-evaluation).
-template <int BS>
+template <int BS, bool REL>
 __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
+    __shared__ float lds_c[REL ? CST_CHUNK * CST_STEP : 1];
     int64_t p, tile;
     const ProbDesc &D = locate<false>(d0, B, p, tile);
     const int64_t i = tile * BS + threadIdx.x;
@@ -229,7 +498,7 @@ __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
     const int64_t j = valid ? i : D.m - 1;
     double X[6];
     init_state(D, j, X);
-    const double J = eval_cost32(D.k, X, lds, lds_ns);
+    const double J = eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c);
     const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
 #pragma unroll
@@ -248,11 +517,12 @@ __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
 
 // Mixed-precision iteration n >= 1: FP32 evaluation and personal best, then
 // the FP64 swarm update towards the FP64-decided global best G_{n-1}.
-template <int BS>
+template <int BS, bool REL>
 __global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, int64_t n)
 {
     __shared__ double lds[OBS_CHUNK * TAB_W];
     __shared__ int32_t lds_ns[OBS_CHUNK];
+    __shared__ float lds_c[REL ? CST_CHUNK * CST_STEP : 1];
     int64_t p, tile;
     const ProbDesc &D = locate<false>(d0, B, p, tile);
     if (B.stop[p] >= 0.0) return;   // ended by Algorithm 2
@@ -269,7 +539,7 @@ __global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, i
     load_state(B.v, ld, gj, V);
     load_state(B.p, ld, gj, Pb);
     double jp = B.jp[gj];
-    const double J = n >= 2 ? eval_cost32(D.k, X, lds, lds_ns) : B.cost[gj];
+    const double J = n >= 2 ? eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c) : B.cost[gj];
     const bool better = cost_key(J) < cost_key(jp);
     if (better) {
         jp = J;
@@ -460,30 +730,52 @@ __global__ __launch_bounds__(64 * RE_WAVES) void k_reeval64(SwarmArrays B,
 // ---------------------------------------------------------------------------
 
 hipError_t launch_propagate32(const KArgs &A, const double *x, int64_t ld, int64_t m,
-                              double *states, hipStream_t st)
+                              double *states, bool rel, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_propagate32, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, states);
+    if (rel && (!A.cst || !A.cpt || !A.cobs)) return hipErrorInvalidValue;
+    if (rel)
+        hipLaunchKernelGGL(k_propagate32<true>, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, states);
+    else
+        hipLaunchKernelGGL(k_propagate32<false>, dim3(grid_for(m, 256)), dim3(256), 0, st, A, x, ld, m, states);
+    return hipGetLastError();
+}
+
+hipError_t launch_chief_stages(const ProbDesc *descs, int64_t nprob, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chief_stages, dim3((unsigned)((nprob + 63) / 64)), dim3(64), 0, st, descs, nprob);
     return hipGetLastError();
 }
 
 hipError_t launch_eval32(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                         hipStream_t st)
+                         bool rel, hipStream_t st)
 {
-    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_eval32<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    if (rel) {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_eval32<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    } else {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_eval32<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_mixed_init(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             hipStream_t st)
+                             bool rel, hipStream_t st)
 {
-    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_init<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    if (rel) {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_init<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    } else {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_init<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B));
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_mixed_iter(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                             int64_t n, hipStream_t st)
+                             int64_t n, bool rel, hipStream_t st)
 {
-    IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_iter<BS_>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    if (rel) {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_iter<BS_, true>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    } else {
+        IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_mixed_iter<BS_, false>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, n));
+    }
     return hipGetLastError();
 }
 

@@ -62,13 +62,16 @@ def test_repeated_batch_solves_match_fresh_batches(torch_dev):
 
     calls = [("fp64", 3, [300, 200, 100], 6), ("fp64", 4, [300, 200, 100], 6),
              ("mixed", 3, [300, 200, 100], 6), ("fp64", 3, [100, 400, 64], 5),
-             ("fp64", 3, [300, 200, 100], 6), ("mixed", 5, [100, 400, 64], 7)]
+             ("mixed_abs", 3, [300, 200, 100], 6), ("fp64", 3, [300, 200, 100], 6),
+             ("mixed", 5, [100, 400, 64], 7), ("mixed_abs", 5, [100, 400, 64], 7)]
     b = make()
 
     def run(bb, kind, seed, m, n):
         m = np.array(m, dtype=np.int64)
         if kind == "fp64":
             return iod.iod_batch_solve(bb, params(seed), m, n)
+        iod.iod_batch_set_fp32_mode(bb, iod.IOD_FP32_ABSOLUTE if kind == "mixed_abs"
+                                    else iod.IOD_FP32_RELATIVE)
         return iod.iod_batch_solve_mixed(bb, params(seed), m, n, top_k=32)
 
     for kind, seed, m, n in calls:
