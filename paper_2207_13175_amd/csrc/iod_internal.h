@@ -26,9 +26,9 @@ constexpr int REC = 8;
 // Chief data of the FP32 propagation, which integrates the deputy's offset
 // from the chief: for each of the four stage inputs C of a chief RK4 step
 // (FP64, the integrator's own order), CST_W floats
-//   d1x = Cx + mu, d2x = Cx - (1 - mu), Cy, Cz,
-//   1/|d1|^2, 1/|d2|^2, (1 - mu)/|d1|^3, mu/|d2|^3,
-// with d_j the chief's offset from primary j.
+//   d2x = Cx - (1 - mu), Cy, Cz, 1/|d1|^2, 1/|d2|^2,
+//   (1 - mu)/|d1|^5, mu/|d2|^5, 1 - (1 - mu)/|d1|^3 - mu/|d2|^3,
+// with d_j the chief's offset from primary j (d1 = d2 + (1, 0, 0)).
 constexpr int CST_W = 8;
 constexpr int CST_STEP = 4 * CST_W;   // floats per RK4 step
 // Steps of chief data staged in LDS at a time; the per-step table carries

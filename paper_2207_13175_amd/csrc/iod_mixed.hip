@@ -24,39 +24,55 @@ namespace iodk {
 //   -mu_j [(d + delta) / b^3 - d / a^3] = -mu_j/a^3 [w^3 delta + (w^3 - 1) d],
 // with d the chief's offset from the primary, a = |d|, b = |d + delta|,
 // u = (b^2 - a^2) / a^2 = (2 d + delta) . delta / a^2, w = (1 + u)^-1/2, and
-//   w^3 - 1 = -u (3 + 3u + u^2) w^6 / (1 + w^3),
+//   w^3 - 1 = -u w^2 (w^2 + w + 1) / (1 + w),
 // so nothing cancels: every rounding error is relative to the perturbation,
 // which is |delta| / |d| (1e-3 to 1e-2) of the attraction itself. The
-// chief-only factors (d, 1/a^2, mu_j/a^3) come per stage from a table the
-// chief kernel writes in FP64 and rounds to FP32. The residual at an
-// observation uses rho = delta itself: no deputy-chief cancellation either.
+// chief-only factors (d, 1/a^2, mu_j/a^5 and the linear coefficient
+// 1 - mu_1/a1^3 - mu_2/a2^3) come per stage from a table the chief kernel
+// writes in FP64 and rounds to FP32. The residual at an observation uses
+// rho = delta itself: no deputy-chief cancellation either.
 // ---------------------------------------------------------------------------
 
+// Attraction term of one primary: e = (mu_j / a^3)(w^3 - 1), from
+// s = b^2 - a^2 = (2 d + delta) . delta, ia = 1/a^2 and kia = mu_j / a^5. With
+// w^2 = 1/(1 + u), u = s ia, and w - 1 = (w^2 - 1)/(w + 1) = -u w^2/(1 + w),
+//   w^3 - 1 = (w - 1)(w^2 + w + 1) = -u w^2 (w^2 + w + 1) / (1 + w).
+// 1/sqrt and 1/x are the hardware FP32 estimates (about 1 ulp).
+__device__ __forceinline__ float attraction_rel(float s, float ia, float kia)
+{
+    const float w = __builtin_amdgcn_rsqf(fmaf(s, ia, 1.0f));
+    const float w2 = w * w;
+    const float wp = w + 1.0f;
+    const float g = fmaf(w, wp, 1.0f);
+    return -(((kia * s) * w2) * g) * __builtin_amdgcn_rcpf(wp);
+}
+
 // Derivative of the offset s = (delta position, delta velocity) at one stage,
-// row = that stage's chief data (CST_W floats). 1/sqrt and 1/x are the
-// hardware FP32 estimates (about 1 ulp).
+// row = that stage's chief data (CST_W floats: d2x, Cy, Cz, 1/a1^2, 1/a2^2,
+// mu_1/a1^5, mu_2/a2^5, T = 1 - mu_1/a1^3 - mu_2/a2^3). With e_j the
+// attraction terms and k_j = mu_j/a_j^3, the perturbing acceleration is
+//   -sum_j k_j [delta + (w_j^3 - 1)(delta + d_j)] = -(K + e1 + e2) delta - sum_j e_j d_j,
+// K = k1 + k2. d1 = d2 + (1, 0, 0) (the primaries are one unit apart), so the
+// x part of the last sum is (e1 + e2) d2x + e1, and s1 = s2 + 2 delta_x. The
+// linear terms of the rotating frame join -(K + e1 + e2) as T - e1 - e2.
 __device__ __forceinline__ void rhs32_rel(const float *row, const float s[6], float f[6])
 {
-    const float d1x = row[0], d2x = row[1], cy = row[2], cz = row[3];
-    const float ia1 = row[4], ia2 = row[5], k1 = row[6], k2 = row[7];
+    const float d2x = row[0], cy = row[1], cz = row[2];
+    const float ia1 = row[3], ia2 = row[4], kia1 = row[5], kia2 = row[6], T = row[7];
     const float dx = s[0], dy = s[1], dz = s[2];
     const float syz = fmaf(fmaf(2.0f, cy, dy), dy, fmaf(2.0f, cz, dz) * dz);
-    const float u1 = fmaf(fmaf(2.0f, d1x, dx), dx, syz) * ia1;
-    const float u2 = fmaf(fmaf(2.0f, d2x, dx), dx, syz) * ia2;
-    const float w1 = __builtin_amdgcn_rsqf(1.0f + u1);
-    const float w2 = __builtin_amdgcn_rsqf(1.0f + u2);
-    const float w13 = w1 * w1 * w1, w23 = w2 * w2 * w2;
-    const float f1 = -(u1 * fmaf(u1, u1 + 3.0f, 3.0f) * (w13 * w13)) * __builtin_amdgcn_rcpf(1.0f + w13);
-    const float f2 = -(u2 * fmaf(u2, u2 + 3.0f, 3.0f) * (w23 * w23)) * __builtin_amdgcn_rcpf(1.0f + w23);
-    const float cs = fmaf(k1, w13, k2 * w23);
-    const float e1 = k1 * f1, e2 = k2 * f2;
+    const float s2 = fmaf(fmaf(2.0f, d2x, dx), dx, syz);
+    const float s1 = fmaf(2.0f, dx, s2);
+    const float e1 = attraction_rel(s1, ia1, kia1);
+    const float e2 = attraction_rel(s2, ia2, kia2);
     const float es = e1 + e2;
+    const float tt = T - es;
     f[0] = s[3];
     f[1] = s[4];
     f[2] = s[5];
-    f[3] = fmaf(2.0f, s[4], dx) - fmaf(cs, dx, fmaf(e1, d1x, e2 * d2x));
-    f[4] = fmaf(-2.0f, s[3], dy) - fmaf(cs, dy, es * cy);
-    f[5] = -fmaf(cs, dz, es * cz);
+    f[3] = fmaf(2.0f, s[4], fmaf(tt, dx, fmaf(-es, d2x, -e1)));
+    f[4] = fmaf(-2.0f, s[3], fmaf(tt, dy, -(es * cy)));
+    f[5] = fmaf(tt - 1.0f, dz, -(es * cz));
 }
 
 // One RK4 step of the offset (stages see D; the increment h/6 (k1 + 2k2 +
@@ -193,23 +209,36 @@ __device__ __forceinline__ void walk32_abs(const KArgs &A, float X[6], float C[6
 }
 
 // FP32 walk of the schedule over the offset from the chief (the default);
-// obs(row, k, D, C) sees the
-// compensated pair at observation k. The chief data of the grid steps is
-// staged through LDS (lds_c, CST_CHUNK steps) by the whole workgroup, whose
-// threads all follow one problem's schedule; a partial step reads its rows
-// from the observation's own table entry.
-template <class Obs>
+// obs(row, k, D, C) sees the compensated pair at observation k. The chief
+// data of the grid steps is staged through LDS (lds_c, CST_CHUNK steps at a
+// time) by the whole workgroup of BS threads, whose threads all follow one
+// problem's schedule; a partial step reads its rows from the observation's
+// own table entry. Chunks are consecutive (steps 0, CST_CHUNK, 2 CST_CHUNK,
+// ...): each thread holds its share of the next chunk in registers, loaded
+// while the current one is in use, so the global-memory latency is not
+// paid at the hand-over. A chunk is fetched only if it starts before the
+// last step, which keeps every read inside the table's CST_CHUNK padding
+// rows.
+template <int BS, class Obs>
 __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6], double *lds,
                                            int32_t *lds_ns, float *lds_c, Obs &obs)
 {
+    constexpr int NPF = CST_CHUNK * CST_STEP / BS;
+    static_assert(NPF * BS == CST_CHUNK * CST_STEP, "a chunk splits evenly over the workgroup");
     const float h = (float)A.h, h2 = 0.5f * h, h6 = h / 6.0f;
+    const int32_t nsteps = A.ns[A.K - 1];
+    float pf[NPF];
+    if (nsteps > 0) {
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) pf[q] = A.cst[threadIdx.x + q * BS];
+    }
     int32_t step = 0, c0 = -CST_CHUNK;
     for (int32_t k0 = 0; k0 < A.K; k0 += OBS_CHUNK) {
         const int32_t nk = min(OBS_CHUNK, A.K - k0);
         __syncthreads();
-        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += blockDim.x)
+        for (int32_t j = threadIdx.x; j < nk * TAB_W; j += BS)
             lds[j] = A.tab[(int64_t)k0 * TAB_W + j];
-        for (int32_t j = threadIdx.x; j < nk; j += blockDim.x) lds_ns[j] = A.ns[k0 + j];
+        for (int32_t j = threadIdx.x; j < nk; j += BS) lds_ns[j] = A.ns[k0 + j];
         __syncthreads();
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
@@ -218,8 +247,13 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
                 if (step >= c0 + CST_CHUNK) {
                     c0 = step;
                     __syncthreads();
-                    for (int32_t j = threadIdx.x; j < CST_CHUNK * CST_STEP; j += blockDim.x)
-                        lds_c[j] = A.cst[(int64_t)c0 * CST_STEP + j];
+#pragma unroll
+                    for (int q = 0; q < NPF; ++q) lds_c[threadIdx.x + q * BS] = pf[q];
+                    if (c0 + CST_CHUNK < nsteps) {
+                        const float *next = A.cst + (int64_t)(c0 + CST_CHUNK) * CST_STEP;
+#pragma unroll
+                        for (int q = 0; q < NPF; ++q) pf[q] = next[threadIdx.x + q * BS];
+                    }
                     __syncthreads();
                 }
                 rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, D, C);
@@ -314,27 +348,28 @@ __device__ __forceinline__ void state32(const double x0[6], float X[6], float C[
     }
 }
 
-// Walk of either formulation: the offset from the chief (REL) or the state.
-template <bool REL, class Obs>
+// Walk of either formulation: the offset from the chief (REL) or the state,
+// by a workgroup of BS threads.
+template <int BS, bool REL, class Obs>
 __device__ __forceinline__ void walk32(const KArgs &A, const double x0[6], double *lds,
                                        int32_t *lds_ns, float *lds_c, Obs &obs)
 {
     float D[6], C[6];
     if (REL) {
         offset32(A, x0, D, C);
-        walk32_rel(A, D, C, lds, lds_ns, lds_c, obs);
+        walk32_rel<BS>(A, D, C, lds, lds_ns, lds_c, obs);
     } else {
         state32(x0, D, C);
         walk32_abs(A, D, C, lds, lds_ns, obs);
     }
 }
 
-template <bool REL>
+template <int BS, bool REL>
 __device__ __forceinline__ double eval_cost32(const KArgs &A, const double x0[6], double *lds,
                                               int32_t *lds_ns, float *lds_c)
 {
     CostAcc32<REL> acc{0.0, (float)A.w, A.mode, (float)A.wr};
-    walk32<REL>(A, x0, lds, lds_ns, lds_c, acc);
+    walk32<BS, REL>(A, x0, lds, lds_ns, lds_c, acc);
     return acc.J;
 }
 
@@ -372,7 +407,7 @@ __global__ __launch_bounds__(256) void k_propagate32(KArgs A, const double *__re
     double x0[6];
     load_state(x, ld, j, x0);
     StoreStates32<REL> obs{A.cobs, states, ld, i, valid};
-    walk32<REL>(A, x0, lds, lds_ns, lds_c, obs);
+    walk32<256, REL>(A, x0, lds, lds_ns, lds_c, obs);
 }
 
 // The chief data of one problem (one thread each): the FP64 RK4 of the
@@ -387,14 +422,16 @@ __device__ __forceinline__ void chief_row(double mu, double mu1, const double s[
     const double q = fma(s[2], s[2], s[1] * s[1]);
     const double a1s = fma(d1x, d1x, q);
     const double a2s = fma(d2x, d2x, q);
-    row[0] = (float)d1x;
-    row[1] = (float)d2x;
-    row[2] = (float)s[1];
-    row[3] = (float)s[2];
-    row[4] = (float)(1.0 / a1s);
-    row[5] = (float)(1.0 / a2s);
-    row[6] = (float)(mu1 / (a1s * sqrt(a1s)));
-    row[7] = (float)(mu / (a2s * sqrt(a2s)));
+    const double k1 = mu1 / (a1s * sqrt(a1s));
+    const double k2 = mu / (a2s * sqrt(a2s));
+    row[0] = (float)d2x;
+    row[1] = (float)s[1];
+    row[2] = (float)s[2];
+    row[3] = (float)(1.0 / a1s);
+    row[4] = (float)(1.0 / a2s);
+    row[5] = (float)(k1 / a1s);
+    row[6] = (float)(k2 / a2s);
+    row[7] = (float)(1.0 - k1 - k2);
 }
 
 __device__ __forceinline__ void chief_step_rows(double mu, double mu1, double h, double h2,
@@ -479,7 +516,7 @@ __global__ __launch_bounds__(BS) void k_eval32(ProbDesc d0, SwarmArrays B)
     const bool valid = i < D.m;
     double X[6];
     load_state(B.x, B.ld, D.off + (valid ? i : D.m - 1), X);
-    const double J = eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c);
+    const double J = eval_cost32<BS, REL>(D.k, X, lds, lds_ns, lds_c);
     if (valid) B.cost[D.off + i] = J;
 }
 
@@ -498,7 +535,7 @@ __global__ __launch_bounds__(BS) void k_mixed_init(ProbDesc d0, SwarmArrays B)
     const int64_t j = valid ? i : D.m - 1;
     double X[6];
     init_state(D, j, X);
-    const double J = eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c);
+    const double J = eval_cost32<BS, REL>(D.k, X, lds, lds_ns, lds_c);
     const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
 #pragma unroll
@@ -539,7 +576,7 @@ __global__ __launch_bounds__(BS) void k_mixed_iter(ProbDesc d0, SwarmArrays B, i
     load_state(B.v, ld, gj, V);
     load_state(B.p, ld, gj, Pb);
     double jp = B.jp[gj];
-    const double J = n >= 2 ? eval_cost32<REL>(D.k, X, lds, lds_ns, lds_c) : B.cost[gj];
+    const double J = n >= 2 ? eval_cost32<BS, REL>(D.k, X, lds, lds_ns, lds_c) : B.cost[gj];
     const bool better = cost_key(J) < cost_key(jp);
     if (better) {
         jp = J;

@@ -100,6 +100,11 @@ def test_calls_reject_null_handle_and_bad_shapes():
     p = iod.pso_params(0.7, 1.5, 1.5, 0, np.zeros(6), np.ones(6))
     assert L.iod_solve(None, C.byref(p), 10, 10, None, None, None) == iod.IOD_EINVAL
     assert L.iod_step(None, None, C.byref(p), 1, None) == iod.IOD_EINVAL
+    for mode in (iod.IOD_FP32_RELATIVE, iod.IOD_FP32_ABSOLUTE, 2, -1):
+        assert L.iod_set_fp32_mode(None, mode) == iod.IOD_EINVAL
+        assert L.iod_batch_set_fp32_mode(None, mode) == iod.IOD_EINVAL
+    assert L.iod_grad_noalloc(None, dummy, 64, 64, dummy, dummy, None) == iod.IOD_EINVAL
+    assert iod.IOD_NOALLOC_SCRATCH_DOUBLES == 1 << 22
 
 
 def _create_ranged_raw(ranges, sigma_range):

@@ -193,6 +193,26 @@ def test_mixed_solve_reports_fp64_results(torch_dev, mode):
     assert np.median(e_mixed) <= 10 * np.median(e_fp64) + 1e-6
 
 
+def test_fp32_mode_rejects_unknown_values(torch_dev):
+    """Only the two FP32 formulations are accepted, on a handle and on a
+    batch."""
+    wl = W.c0(0)
+    obs = np.zeros((wl.K, 2))
+    h = iod.iod_create(wl.mu, wl.chief, wl.t, obs, wl.sigma, h=wl.h)
+    b = iod.iod_create_batch([wl.mu], [wl.chief], [wl.t], [obs], [wl.sigma], h=wl.h)
+    for bad in (2, -1, 1 << 20):
+        with pytest.raises(iod.IodError) as e:
+            iod.iod_set_fp32_mode(h, bad)
+        assert e.value.code == iod.IOD_EINVAL
+        with pytest.raises(iod.IodError) as e:
+            iod.iod_batch_set_fp32_mode(b, bad)
+        assert e.value.code == iod.IOD_EINVAL
+    iod.iod_set_fp32_mode(h, iod.IOD_FP32_ABSOLUTE)
+    iod.iod_batch_set_fp32_mode(b, iod.IOD_FP32_ABSOLUTE)
+    iod.iod_batch_destroy(b)
+    iod.iod_destroy(h)
+
+
 def test_mixed_top_k_all_equals_fp64_ranking_on_graph_and_eager(torch_dev):
     """Graph replay and eager launches of the mixed pipeline agree bit for bit."""
     wl = small_batch(4, P=5)
