@@ -192,7 +192,6 @@ def fp32_leg_mode(iod, torch, wl, obs, x, steps_per_eval, mode, reps):
     return {"particle_steps_per_s": wl.m * steps_per_eval / (t32 * 1e-3), "eval_ms": t32,
             "fp64_eval_ms": t64, "speedup_vs_fp64_eval": t64 / t32,
             "algorithmic_tflops": tf, "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
-            "frac_of_fp32_unpacked_peak": tf / PEAK_FP64_TFLOPS,
             "cost_rel_err_vs_fp64_q50_q99_max": [float(np.quantile(rel, 0.5)),
                                                  float(np.quantile(rel, 0.99)), float(np.max(rel))]}
 
@@ -500,8 +499,7 @@ def batched_legs(iod, torch):
             # k_reeval64 (mixed), HIP events on the solve's stream
             "ms_per_iter": it_ms,
             "algorithmic_tflops": tf,
-            **({"frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
-                "frac_of_fp32_unpacked_peak": tf / PEAK_FP64_TFLOPS} if top_k
+            **({"frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS} if top_k
                else {"frac_of_fp64_peak": tf / PEAK_FP64_TFLOPS}),
             "pos_err_q10_50_90_lu": q(err),
             "finite_costs": int(np.sum(np.isfinite(J))),
