@@ -47,6 +47,12 @@ PEAK_CLOCK_GHZ = 2.4     # the clock the published peaks assume
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
 # sources the FP64 iteration kernel is built from
+# Gauss-Newton iteration cap of the refinement workload. Problems retire as
+# they converge, so the cap costs only while some are still moving: at 40
+# every one of the 4,096 problems reaches its minimum on both routes (4,092
+# at 20, 6% faster).
+GN_CAP = 40
+
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_13175_amd", "csrc", f)
                for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
 
@@ -522,13 +528,13 @@ def batched_legs(iod, torch):
         cfg, _ = iod.iod_batch_autotune(b, params, wl.m, trial_iters=3, top_k=64)
         t0 = time.perf_counter()
         g, chi2, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64,
-                                                  n_cand=16, n_gn=20)
+                                                  n_cand=16, n_gn=GN_CAP)
         runs[mode] = (g, time.perf_counter() - t0, iod.iod_batch_last_iter_ms(b), cfg)
     g, el, mixed_iter_ms, cfg = runs[iod.IOD_FP32_ABSOLUTE]
     g_rel, el_rel, rel_iter_ms, _ = runs[iod.IOD_FP32_RELATIVE]
     t0 = time.perf_counter()
     g64, chi64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
-                                                 n_gn=20)
+                                                 n_gn=GN_CAP)
     el64 = time.perf_counter() - t0
     iod.iod_batch_destroy(b)
     dpol = np.max(np.abs(g - g64), axis=1)
@@ -536,7 +542,7 @@ def batched_legs(iod, torch):
     err = np.linalg.norm(g[:, :3] - wl.truth[:, :3], axis=1)
     e64 = np.linalg.norm(g64[:, :3] - wl.truth[:, :3], axis=1)
     out["c4"] = {
-        "workload": wl.name + "_mixed_top64_refine16x20", "dtype": "f32+f64",
+        "workload": wl.name + f"_mixed_top64_refine16x{GN_CAP}", "dtype": "f32+f64",
         "fp32_formulation": "absolute state",
         "problems": wl.P, "particles": int(wl.m.sum()), "iterations": wl.n_iter,
         "problem_solves_per_s": wl.P / el, "ms_per_solve": el * 1e3,
@@ -572,7 +578,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--iters", type=int, default=None, help="override PSO iterations")
-    ap.add_argument("--gn-iters", type=int, default=20,
+    ap.add_argument("--gn-iters", type=int, default=GN_CAP,
                     help="Gauss-Newton iteration cap of the refinement workload")
     ap.add_argument("--n-cand", type=int, default=16,
                     help="personal bests refined per problem in the refinement workload")

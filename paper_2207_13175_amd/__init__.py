@@ -618,7 +618,7 @@ def iod_batch_polish(batch: Batch, x, m, n_iter, chi2, work=None, stream=None):
                                   int(n_iter), _dev(chi2, (ld,)), _dev(work), _stream(stream)))
 
 
-def iod_batch_solve_polished(batch: Batch, params, m, n_iter, top_k=64, n_cand=16, n_gn=20):
+def iod_batch_solve_polished(batch: Batch, params, m, n_iter, top_k=64, n_cand=16, n_gn=40):
     """(best states [P, 6], best chi2 [P], best costs [P]) after the swarm and
     the Gauss-Newton refinement of each problem's n_cand best personal bests."""
     m = np.ascontiguousarray(m, dtype=np.int64)

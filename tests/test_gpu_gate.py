@@ -1,7 +1,7 @@
 """The precision gate of the mixed-precision route on a sample of the
 refinement workload: 256 of its 4,096 problems (10-60 observations over
 0.5-2.5 TU, 2,048 particles, 100 swarm iterations, then Gauss-Newton on 16
-candidates with the default cap of 20 iterations).
+candidates with the default cap of 40 iterations).
 
 - Every problem's refined state after the mixed swarm (FP32 ranking, FP64
   global best) lies within 1e-9 of the refined state after the plain FP64
@@ -52,9 +52,9 @@ def gate_run():
     params = [iod.pso_params(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p],
                              problem=p) for p in range(wl.P)]
     gm, cm, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=64, n_cand=16,
-                                             n_gn=20)
+                                             n_gn=40)
     g64, c64, _ = iod.iod_batch_solve_polished(b, params, wl.m, wl.n_iter, top_k=0, n_cand=16,
-                                               n_gn=20)
+                                               n_gn=40)
     return wl, probs, gm, cm, g64, c64
 
 
