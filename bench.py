@@ -268,8 +268,18 @@ def batch_with_observations(iod, wl, ranges=False):
                                 obs_ranges=rg, sigma_range=[W.SIGMA_RANGE] * wl.P)
 
 
+def fp32_name(args):
+    """The FP32 formulation of a mixed-precision workload: as asked, else the
+    absolute state for the refinement workload (the refinement sets its final
+    accuracy, so the faster ranking serves) and the offset from the chief
+    for the swarm without refinement."""
+    if args.fp32_mode is not None:
+        return args.fp32_mode
+    return "absolute" if args.workload == "c4" else "offset"
+
+
 def fp32_mode_of(args, iod):
-    return iod.IOD_FP32_ABSOLUTE if args.fp32_mode == "absolute" else iod.IOD_FP32_RELATIVE
+    return iod.IOD_FP32_ABSOLUTE if fp32_name(args) == "absolute" else iod.IOD_FP32_RELATIVE
 
 
 def run_refine(args, iod, torch):
@@ -324,7 +334,7 @@ def run_refine(args, iod, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name + f"_mixed_top64_refine{n_cand}x{n_gn}", "problems": wl.P,
-                   "fp32_formulation": args.fp32_mode,
+                   "fp32_formulation": fp32_name(args),
                    "particles": int(wl.m.sum()), "iterations": wl.n_iter,
                    "steps_range": [int(steps.min()), int(steps.max())],
                    "particle_steps_per_solve": ps,
@@ -434,7 +444,7 @@ def run_batch(args, iod, torch, top_k=0):
         "config": {"workload": wl.name + (f"_mixed_top{top_k}" if top_k else "")
                                + ("" if args.variant == "none" else "_" + args.variant),
                    "variant": args.variant,
-                   **({"fp32_formulation": args.fp32_mode} if top_k else {}),
+                   **({"fp32_formulation": fp32_name(args)} if top_k else {}),
                    "iterations_run_q10_50_90": [float(np.quantile(n_run, v)) for v in (0.1, 0.5, 0.9)],
                    "mixed_vs_fp64": compare, "problems": wl.P, "particles": int(wl.m.sum()),
                    "iterations": wl.n_iter, "obs_range": [int(wl.K.min()), int(wl.K.max())],
@@ -584,9 +594,9 @@ def main():
                     help="personal bests refined per problem in the refinement workload")
     ap.add_argument("--variant", default="none", choices=VARIANTS,
                     help="one of the paper's variants beside Algorithm 1")
-    ap.add_argument("--fp32-mode", choices=("offset", "absolute"), default="offset",
-                    help="FP32 formulation of the mixed-precision workloads (c3, c4): the "
-                         "offset from the chief (default) or the absolute state")
+    ap.add_argument("--fp32-mode", choices=("offset", "absolute"), default=None,
+                    help="FP32 formulation of the mixed-precision workloads: the offset from "
+                         "the chief (default for c3) or the absolute state (default for c4)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
