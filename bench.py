@@ -45,28 +45,41 @@ PEAK_FP64_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # FP32 vector (dual-issue/packed), published figure
 PEAK_CLOCK_GHZ = 2.4     # the clock the published peaks assume
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
-# sources the FP64 iteration kernel is built from
 # Gauss-Newton iteration cap of the refinement workload. Problems retire as
 # they converge, so the cap costs only while some are still moving: at 40
 # every one of the 4,096 problems reaches its minimum on both routes (4,092
 # at 20, 6% faster).
 GN_CAP = 40
 
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_13175_amd", "csrc", f)
-               for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_swarm_iter_c1_traffic.txt")
+FP32_COUNTER_FILE = os.path.join(ROOT, "profiles", "k_eval32_c1_fp32_counters.txt")
+CSRC = os.path.join(ROOT, "paper_2207_13175_amd", "csrc")
+# sources the FP64 iteration kernel is built from
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("iod_kernels.hip", "iod_device.h", "iod_internal.h")]
 
 
-def kernel_hash() -> str:
-    """Hash of what shapes the iteration kernel's code: its sources and the
-    compiler flags of its file."""
+def kernel_hash(unit="iod_kernels.hip") -> str:
+    """Hash of what shapes the kernels of one source file: the file, the
+    device headers it includes and its compiler flags."""
     from paper_2207_13175_amd import build as B
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in [os.path.join(CSRC, unit)] + KERNEL_SRCS[1:]:
         with open(path, "rb") as f:
             h.update(f.read())
-    h.update(repr(B.ARCH + B.FLAGS + dict(B.UNITS)["iod_kernels.hip"]).encode())
+    h.update(repr(B.ARCH + B.FLAGS + dict(B.UNITS)[unit]).encode())
     return h.hexdigest()[:16]
+
+
+def read_summary(path, unit):
+    """key: value lines of a committed counter summary, or None if the
+    sources of `unit` changed since the counters were taken."""
+    try:
+        with open(path) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    return kv if kv.get("kernel_sha") == kernel_hash(unit) else None
 
 
 def load_counters():
@@ -76,15 +89,9 @@ def load_counters():
     quad-cycles per wave per RK4 step (SQ_ACTIVE_INST_VALU) and the clock
     during the launch; None for all if the kernel sources changed since the
     counters were taken."""
-    none = (None, None, None, None)
-    try:
-        with open(TRAFFIC_FILE) as f:
-            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
-    except OSError:
-        return none
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_sha") != kernel_hash():
-        return none
+    kv = read_summary(TRAFFIC_FILE, "iod_kernels.hip")
+    if kv is None:
+        return (None, None, None, None)
     return (float(kv["hbm_bytes_per_launch"]), float(kv["total_64_ops_per_eval_launch"]),
             float(kv["valu_quad_cycles_per_wave_step"]), float(kv["clock_ghz"]))
 
@@ -195,8 +202,14 @@ def fp32_leg_mode(iod, torch, wl, obs, x, steps_per_eval, mode, reps):
     rel = np.abs(a32 - a64) / np.abs(a64)
     flop = wl.m * (steps_per_eval * FLOP_PER_STEP + wl.K * FLOP_PER_OBS)
     tf = flop / (t32 * 1e-3) / 1e12
+    # counted FP32 operations of the same evaluation ((2 FMA + MUL + ADD) x 64
+    # per launch, from the committed counter summary) over the measured time
+    kv = read_summary(FP32_COUNTER_FILE, "iod_mixed.hip") if wl.m == 65536 else None
+    key = "total_32_ops_" + ("offset" if mode == iod.IOD_FP32_RELATIVE else "absolute")
+    ctf = float(kv[key]) / (t32 * 1e-3) / 1e12 if kv and key in kv else None
     return {"particle_steps_per_s": wl.m * steps_per_eval / (t32 * 1e-3), "eval_ms": t32,
             "fp64_eval_ms": t64, "speedup_vs_fp64_eval": t64 / t32,
+            "counter_tflops": ctf, "counter_frac_of_fp32_peak": ctf / PEAK_FP32_TFLOPS if ctf else None,
             "algorithmic_tflops": tf, "frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS,
             "cost_rel_err_vs_fp64_q50_q99_max": [float(np.quantile(rel, 0.5)),
                                                  float(np.quantile(rel, 0.99)), float(np.max(rel))]}

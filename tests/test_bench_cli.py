@@ -29,3 +29,18 @@ def test_counter_record_is_tied_to_the_kernel_sources():
         assert c["frac_at_measured_clock"] <= c["frac_at_2.4GHz_full_busy"] <= 1.0
     else:
         assert traffic is None and ops is None and valu is None and clock is None
+
+
+def test_fp32_counter_record_is_tied_to_the_fp32_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    kv = bench.read_summary(bench.FP32_COUNTER_FILE, "iod_mixed.hip")
+    with open(bench.FP32_COUNTER_FILE) as f:
+        sha = [l.split(":", 1)[1].strip() for l in f if l.startswith("kernel_sha")][0]
+    if sha == bench.kernel_hash("iod_mixed.hip"):
+        # the offset formulation does more arithmetic per step than the absolute one
+        assert float(kv["total_32_ops_offset"]) > float(kv["total_32_ops_absolute"]) > 0
+    else:
+        assert kv is None
+    # the FP64 record is keyed by another file's sources
+    assert bench.kernel_hash("iod_mixed.hip") != bench.kernel_hash()
