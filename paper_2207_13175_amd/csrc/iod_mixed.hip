@@ -75,12 +75,23 @@ __device__ __forceinline__ void rhs32_rel(const float *row, const float s[6], fl
     f[5] = fmaf(tt - 1.0f, dz, -(es * cz));
 }
 
+// A double as an unevaluated float pair hi + lo (|lo| <= ulp(hi) / 2).
+__device__ __forceinline__ void float_pair(double v, float &hi, float &lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
 // One RK4 step of the offset (stages see D; the increment h/6 (k1 + 2k2 +
 // 2k3 + k4) is added with Kahan compensation, C holding minus the lost low
-// part, so the accumulated offset is D - C). rows: the step's four stage
-// rows of chief data.
+// part, so the accumulated offset is D - C). h/6 enters as the float pair
+// h6 + h6lo: the chief's FP64 steps are exact multiples of h, and an
+// offset stepped with h/6 rounded to float would drift against them (in a
+// float32 emulation of the large swarm the pair cuts the position error
+// from 1.9e-8 to 3.3e-10 LU). rows: the step's four stage rows of chief
+// data.
 __device__ __forceinline__ void rk4_32_rel(const float *rows, float h, float h2, float h6,
-                                           float D[6], float C[6])
+                                           float h6lo, float D[6], float C[6])
 {
     float k[6], a[6], s[6];
     rhs32_rel(rows, D, k);
@@ -105,7 +116,7 @@ __device__ __forceinline__ void rk4_32_rel(const float *rows, float h, float h2,
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = a[d] + k[d];
-        const float yv = fmaf(h6, a[d], -C[d]);
+        const float yv = fmaf(h6, a[d], fmaf(h6lo, a[d], -C[d]));
         const float t = D[d] + yv;
         C[d] = (t - D[d]) - yv;
         D[d] = t;
@@ -225,7 +236,9 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
 {
     constexpr int NPF = CST_CHUNK * CST_STEP / BS;
     static_assert(NPF * BS == CST_CHUNK * CST_STEP, "a chunk splits evenly over the workgroup");
-    const float h = (float)A.h, h2 = 0.5f * h, h6 = h / 6.0f;
+    const float h = (float)A.h, h2 = 0.5f * h;
+    float h6, h6lo;
+    float_pair(A.h / 6.0, h6, h6lo);
     const int32_t nsteps = A.ns[A.K - 1];
     float pf[NPF];
     if (nsteps > 0) {
@@ -256,7 +269,7 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
                     }
                     __syncthreads();
                 }
-                rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, D, C);
+                rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, h6lo, D, C);
             }
             const float tau = (float)row[TAB_TAU];
             float S[6], SC[6];
@@ -265,8 +278,11 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
                 S[d] = D[d];
                 SC[d] = C[d];
             }
-            if (tau != 0.0f)
-                rk4_32_rel(A.cpt + (int64_t)(k0 + kk) * CST_STEP, tau, 0.5f * tau, tau / 6.0f, S, SC);
+            if (tau != 0.0f) {
+                float t6, t6lo;
+                float_pair(row[TAB_TAU] / 6.0, t6, t6lo);
+                rk4_32_rel(A.cpt + (int64_t)(k0 + kk) * CST_STEP, tau, 0.5f * tau, t6, t6lo, S, SC);
+            }
             obs(row, k0 + kk, S, SC);
         }
     }
@@ -288,14 +304,14 @@ __device__ __forceinline__ void entry_pad()
 // formulation). The absolute formulation's iteration on the uneven batch
 // takes 15.8-16.5 ms when its RK4 loop starts at 8 or 16 mod 32 bytes and
 // 17.8-19.0 ms at the other six offsets, with the same instructions; these
-// paddings put every absolute-state instance at 8 mod 32 and give each
-// offset-formulation instance its fastest measured placement (within 3% of
-// its slowest). A change to this file or to the device code it includes
-// moves the loops: the placement test then names the instance to retune.
+// paddings put every absolute-state instance at 8 mod 32. The offset
+// formulation's iteration moved by at most 3% over the same sweep and takes
+// none. A change to this file or to the device code it includes moves the
+// loops: the placement test then names the instance to retune.
 template <int BS, bool REL>
 constexpr int iter_pad()
 {
-    return REL ? (BS == 64 ? 5 : BS == 128 ? 6 : 4) : (BS == 64 ? 6 : 4);
+    return REL ? 0 : (BS == 64 ? 6 : 4);
 }
 
 // FP32 residual cost. REL: rho is the compensated offset S - C at the
