@@ -159,18 +159,31 @@ def observe_single(wl):
 
 
 def test_batch_full_size_sampled(torch_dev):
-    """The full uneven batch (1,024 problems, 2.9 M particles) for two
-    iterations: sampled problems equal their single-problem solves bit for
-    bit, and every global best is the oracle's cost of its own state."""
-    wl = W.c2(0, n_iter=2)
+    """The full uneven batch (1,024 problems, 2.9 M particles) for three
+    iterations in the benchmark's usual launch configuration (64-lane
+    workgroups, longest first, one graph): sampled problems equal their
+    single-problem solves bit for bit, the problems with the most particles
+    and the most steps equal the oracle's own run of Algorithm 1 (global
+    best state bitwise, costs within the bar), and every global best is the
+    oracle's cost of its own state."""
+    wl = W.c2(0, n_iter=3)
     probs, obs = observe(wl)
     b = make_batch(wl, obs)
+    iod.iod_batch_set_config(b, block=64, order=iod.IOD_ORDER_LONGEST_FIRST, graph=1)
     g, J, hist = iod.iod_batch_solve(b, params_of(wl), wl.m, wl.n_iter)
     assert np.all(hist[:, 1:] <= hist[:, :-1])
     for p in (0, 1, int(np.argmax(wl.m)), int(np.argmax(wl.steps())), wl.P - 1):
         h1 = iod.iod_create(wl.mu, wl.chief[p], wl.t[p], obs[p], wl.sigma, h=wl.h)
         g1, J1, _ = iod.iod_solve(h1, params_of(wl)[p], int(wl.m[p]), wl.n_iter)
         assert np.array_equal(g1, g[p]) and J1 == J[p], p
+    for p in {int(np.argmax(wl.m)), int(np.argmax(wl.steps()))}:
+        S = oracle.Pso(wl.omega, wl.eta1, wl.eta2, wl.pso_seed, wl.lo[p], wl.hi[p], problem=p)
+        g_ref, J_ref, h_ref, _ = oracle.pso_solve(probs[p], S, int(wl.m[p]), wl.n_iter)
+        print(f"problem {p}: m = {wl.m[p]}, {wl.steps()[p]} steps: global best {J[p]:.6e} "
+              f"(oracle {J_ref:.6e})")
+        assert np.array_equal(g[p], g_ref), p
+        assert abs(J[p] - J_ref) <= COST_RTOL * abs(J_ref), p
+        assert np.all(np.abs(hist[p] - h_ref) <= COST_RTOL * np.abs(h_ref)), p
     for p in range(0, wl.P, 97):
         want = oracle.cost(probs[p], g[p][None, :])[0]
         if np.isfinite(want):
