@@ -501,6 +501,24 @@ def batched_legs(iod, torch):
     steps = iod.iod_batch_steps(b)
     ps = int(wl.n_iter) * int(np.sum(wl.m * steps))
     flop_iter = float(np.sum(wl.m * (steps * FLOP_PER_STEP + wl.K * FLOP_PER_OBS + FLOP_PER_UPDATE)))
+    ones = np.ones(wl.P, dtype=np.int64)
+    off1 = iod.iod_batch_offsets(b, ones)
+
+    def fp32_vs_fp64_at(states):
+        """FP32 against FP64 costs of each problem's state (one column per
+        problem), in the batch's current FP32 formulation."""
+        x = torch.zeros((6, int(off1[-1])), dtype=torch.float64, device="cuda")
+        x[:, torch.from_numpy(off1[:-1]).cuda()] = torch.from_numpy(np.ascontiguousarray(states.T)).cuda()
+        c32 = torch.empty(int(off1[-1]), dtype=torch.float64, device="cuda")
+        c64 = torch.empty_like(c32)
+        iod.iod_batch_eval_f32(b, x, ones, c32)
+        iod.iod_batch_eval(b, x, ones, c64)
+        torch.cuda.synchronize()
+        a32, a64 = c32.cpu().numpy()[off1[:-1]], c64.cpu().numpy()[off1[:-1]]
+        ok = np.isfinite(a64) & (a64 != 0)
+        return np.abs(a32[ok] - a64[ok]) / np.abs(a64[ok])
+
+    g64_c2 = J64_c2 = None
     for key, top_k, mode in (("c2", 0, None), ("c3", 64, iod.IOD_FP32_RELATIVE),
                              ("c3_absolute", 64, iod.IOD_FP32_ABSOLUTE)):
         if mode is not None:
@@ -534,6 +552,19 @@ def batched_legs(iod, torch):
             "finite_costs": int(np.sum(np.isfinite(J))),
             "autotuned": {"block": cfg.block, "order": cfg.order, "graph": cfg.graph,
                           "waves": cfg.waves}}
+        if top_k:
+            # against the FP64 swarm of the same batch (c2): the final states and
+            # costs, and the FP32 cost error at the final states (the noise floor)
+            d = np.max(np.abs(g - g64_c2), axis=1)
+            rel = fp32_vs_fp64_at(g)
+            out[key]["vs_fp64_swarm"] = {
+                "final_state_diff_q10_50_90": q(d),
+                "final_cost_ratio_q10_50_90": q(J / J64_c2),
+                "same_final_state": int(np.sum(d == 0.0)),
+                "fp32_cost_rel_err_at_final_states_q50_q99_max": [
+                    float(np.quantile(rel, 0.5)), float(np.quantile(rel, 0.99)), float(np.max(rel))]}
+        else:
+            g64_c2, J64_c2 = g, J
         print(f"# {key}: {wl.P / el:.1f} problem solves/s, {it_ms:.2f} ms per iteration",
               file=sys.stderr, flush=True)
     out["c3"]["absolute_formulation"] = out.pop("c3_absolute")
