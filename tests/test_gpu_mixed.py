@@ -111,6 +111,59 @@ def test_f32_propagation_partial_steps_and_close_approach(torch_dev, case, mode,
     assert err <= bound
 
 
+@pytest.mark.parametrize("mode", [iod.IOD_FP32_RELATIVE, iod.IOD_FP32_ABSOLUTE])
+def test_f32_extreme_particles(torch_dev, mode):
+    """FP32 evaluation of particles outside any sensible box in the same
+    waves as ordinary ones: a NaN state, states beyond the float range, on
+    either primary, next to the smaller one, on the chief. The ordinary
+    particles' costs equal their costs evaluated without the extreme ones
+    (no lane affects another), a NaN state gives a non-finite cost, the
+    chief itself gives +inf in the offset formulation (zero line of sight),
+    and the ordinary costs stay within the FP32 bars of
+    test_f32_cost_error_stated."""
+    torch, dev = torch_dev
+    wl = W.c0(0)
+    P0 = oracle.Problem(wl.mu, wl.h, wl.sigma, wl.chief, wl.t, np.zeros((wl.K, 2)))
+    obs = oracle.predict(P0, wl.truth) + wl.noise
+    P = P0.with_angles(obs)
+    extreme = np.vstack([
+        wl.chief,
+        [np.nan, 0, 0, 0, 0, 0],
+        [-wl.mu, 0, 0, 0, 0, 0],
+        [1 - wl.mu, 0, 0, 0, 0, 0],
+        [1e300, 0, 0, 0, 0, 0],
+        [3e54, 0, 0, 0, 0, 0],
+        [1e20, 1e20, 0, 0, 0, 0],
+        [1 - wl.mu + 1e-120, 1e-130, 0, 0, 1.0, 0],
+    ])
+    ordinary = W.random_swarm(4, 56, wl.lo, wl.hi)
+    b = iod.iod_create_batch([wl.mu], [wl.chief], [wl.t], [obs], [wl.sigma], h=wl.h)
+    iod.iod_batch_set_fp32_mode(b, mode)
+
+    def costs(xs):
+        x = to_dev(torch, dev, xs)
+        c = torch.full((x.shape[1],), -7.0, dtype=torch.float64, device=dev)
+        iod.iod_batch_eval_f32(b, x, np.array([len(xs)]), c)
+        torch.cuda.synchronize()
+        return c.cpu().numpy()[:len(xs)]
+
+    mixed = costs(np.vstack([ordinary[:28], extreme, ordinary[28:]]))
+    alone = costs(ordinary)
+    got_ord = np.concatenate([mixed[:28], mixed[28 + len(extreme):]])
+    assert np.array_equal(got_ord, alone)
+    assert np.all(np.isfinite(alone))
+    got_ext = mixed[28:28 + len(extreme)]
+    assert not np.isfinite(got_ext[1])
+    if mode == iod.IOD_FP32_RELATIVE:
+        assert got_ext[0] == np.inf
+    want = oracle.cost(P, ordinary)
+    rel = np.abs(alone - want) / want
+    if mode == iod.IOD_FP32_RELATIVE:
+        assert np.all(rel <= 1e-5), rel.max()
+    else:
+        assert np.all(rel[want > 1e8] <= 0.05), rel[want > 1e8].max()
+
+
 def small_batch(seed=0, P=8):
     wl = W.c2(seed, P=P, n_iter=12, m_range=(100, 400), K_range=(3, 12), T_range=(0.05, 0.4))
     return wl
