@@ -305,13 +305,14 @@ __device__ __forceinline__ void entry_pad()
 // takes 15.8-16.5 ms when its RK4 loop starts at 8 or 16 mod 32 bytes and
 // 17.8-19.0 ms at the other six offsets, with the same instructions; these
 // paddings put every absolute-state instance at 8 mod 32. The offset
-// formulation's iteration moved by at most 3% over the same sweep and takes
-// none. A change to this file or to the device code it includes moves the
-// loops: the placement test then names the instance to retune.
+// formulation's iteration moves by less than 2% over the eight paddings;
+// each instance takes its fastest measured one. A change to this file or to
+// the device code it includes moves the loops: the placement test then
+// names the absolute-state instance to retune.
 template <int BS, bool REL>
 constexpr int iter_pad()
 {
-    return REL ? 0 : (BS == 64 ? 6 : 4);
+    return REL ? (BS == 256 ? 4 : 5) : (BS == 64 ? 6 : 4);
 }
 
 // FP32 residual cost. REL: rho is the compensated offset S - C at the
