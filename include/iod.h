@@ -548,24 +548,27 @@ int iod_batch_polish(iod_batch *b, double *x, int64_t ld, const int64_t *m, int3
  * in iod_batch_solve_mixed), then at most n_gn damped Gauss-Newton iterations
  * on each of the problem's n_cand (1..64) candidates, keeping the one with
  * the lowest chi2. The candidates are the problem's global best (decided by
- * FP64 costs on both routes) and its lowest-cost other personal bests (by
- * the swarm's own costs, FP32 in mixed precision), min(n_cand, m) in all.
- * Each iteration tries T = min(8, 64 / n_cand) dampings per candidate,
- * lambda 10^(k - T/2) for k < T, each step v with its geodesic-acceleration
- * correction a (from the residuals at x + 0.1 v) added as v + a/2 when
- * 2|a| <= 0.75|v|, and keeps the trial with the lowest chi2 if it is below
- * the candidate's (lambda becomes that trial's / 10; if none is lower,
- * 10 x the largest tried). Problems stop as they converge, so a generous
- * n_gn costs only while some problem is still moving (40 brings every
- * problem of the 4,096-problem refinement workload to its minimum, 20 all
- * but 4). A candidate stops once its accepted step, or every trial step when none is accepted, is at
- * most 1e-12 in every component, or lambda reaches 1e12; a problem stops when
- * all its candidates have. With n_gn >= 1 every candidate then takes up to
- * two undamped Gauss-Newton steps, each applied only if no component exceeds
- * 1e-6 (near the minimum the binary64 chi2 is too noisy to decide the last
- * steps along weakly observed directions; the steps themselves are not).
- * Outputs (host): best_states [P][6], best_chi2 [P] (may be NULL) and
- * best_costs [P] (the problem's own cost mode, may be NULL). Synchronous. */
+ * FP64 costs on both routes) and its lowest-cost other personal bests (by the
+ * swarm's own costs, FP32 in mixed precision), min(n_cand, m) in all. Each
+ * iteration forms J^T J of the whitened residuals in a forward tangent sweep
+ * and the gradient of chi2 (the steps' right-hand side) by the discrete
+ * adjoint, per candidate, and tries T = min(8, 64 / n_cand) dampings per
+ * candidate, lambda 10^(k - T/2) for k < T, each step v with its
+ * geodesic-acceleration correction a (from the residuals at x + 0.1 v) added
+ * as v + a/2 when 2|a| <= 0.75|v|, and keeps the trial with the lowest chi2
+ * if it is below the candidate's (lambda becomes that trial's / 10; if none
+ * is lower, 10 x the largest tried). Problems stop as they converge, so a
+ * generous n_gn costs only while some problem is still moving (40 brings
+ * every problem of the 4,096-problem refinement workload to its minimum, 20
+ * all but 4). A candidate stops once its accepted step, or every trial step
+ * when none is accepted, is at most 1e-12 in every component, or lambda
+ * reaches 1e12; a problem stops when all its candidates have. With n_gn >= 1
+ * every candidate then takes up to two undamped Gauss-Newton steps, each
+ * applied only if no component exceeds 1e-6 (near the minimum the binary64
+ * chi2 is too noisy to decide the last steps along weakly observed
+ * directions; the steps themselves are not). Outputs (host): best_states
+ * [P][6], best_chi2 [P] (may be NULL) and best_costs [P] (the problem's own
+ * cost mode, may be NULL). Synchronous. */
 int iod_batch_solve_polished(iod_batch *b, const iod_pso_params *params, const int64_t *m,
                              int64_t n_iter, int32_t top_k, int32_t n_cand, int32_t n_gn,
                              double *best_states, double *best_chi2, double *best_costs);

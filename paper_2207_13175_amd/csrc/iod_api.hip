@@ -1587,7 +1587,9 @@ int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
     // steps first. Each iteration they take only the live pairs (problem
     // active, candidate not done), compacted in that order after the select
     // step, so retired pairs leave the waves; the grid stays that of all
-    // pairs and the waves past the live count exit at once.
+    // pairs and the waves past the live count exit at once. Both sweeps go
+    // in one launch, so that the tangent and the adjoint sweep of the last
+    // live pairs run at the same time.
     Lanes KL;
     KL.pairs = lanes;
     KL.n = nlanes;
@@ -1598,10 +1600,10 @@ int polish_trials_run(const ProbDesc &d0, SwarmArrays PB, const ProbDesc *tdesc,
     const int64_t kgrid = (nlanes + 63) / 64;
     HIP_TRY(launch_live_lanes(lanes, nlanes, active, done, live, live_count, st));
     for (int32_t it = 0; it < n_iter; ++it) {
-        HIP_TRY(launch_normal(d0, PB, 64, kgrid, chi2, jtj, jtr, st, jrows, n_cand, jld, LL));
         SwarmArrays GB = PB;
         GB.cost = cost;
-        HIP_TRY(launch_grad(d0, GB, 64, kgrid, g, adj, ld, 1, st, LL));
+        HIP_TRY(launch_normal_grad(d0, PB, GB, kgrid, chi2, jtj, jtr, jrows, n_cand, jld, g, adj,
+                                   ld, 1, st, LL));
         HIP_TRY(launch_gn_trials(x, jtj, g, lam, n, active, done, T, P, ld, xt, vt, st));
         HIP_TRY(launch_geo(PB.desc, x, jtj, jtr, jrows, n_cand, jld, lam, n, active, done, T, P,
                            ld, GEO_HD, GEO_ALPHA, vt, xt, st));

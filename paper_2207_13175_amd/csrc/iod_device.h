@@ -591,15 +591,16 @@ __device__ __forceinline__ const ProbDesc &locate(const ProbDesc &d0, const Swar
 // (one problem per workgroup); PACKED, one (problem, particle) pair per
 // thread from L, so that a wave can hold the candidates of several problems.
 // Returns false for a thread with nothing to do (past the lanes, or its
-// problem inactive; uniform over the workgroup unless PACKED).
+// problem inactive; uniform over the workgroup unless PACKED). blk is the
+// PACKED workgroup's index among the lanes' workgroups.
 enum { PLACE_SINGLE = 0, PLACE_BATCH = 1, PLACE_PACKED = 2 };
 
 template <int BS, int PLACE>
 __device__ __forceinline__ bool place(const ProbDesc &d0, const SwarmArrays &B, const Lanes &L,
-                                      int64_t &p, int64_t &i, const ProbDesc *&D)
+                                      int64_t blk, int64_t &p, int64_t &i, const ProbDesc *&D)
 {
     if (PLACE == PLACE_PACKED) {
-        const int64_t q = (int64_t)blockIdx.x * BS + threadIdx.x;
+        const int64_t q = blk * BS + threadIdx.x;
         if (q >= (L.count ? *L.count : L.n)) return false;
         p = L.pairs[2 * q];
         i = L.pairs[2 * q + 1];

@@ -68,6 +68,12 @@ hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64
                          double *chi2, double *jtj, double *jtr, hipStream_t st,
                          double *jrows = nullptr, int64_t jstride = 0, int64_t jld = 0,
                          const Lanes &L = Lanes());
+// launch_normal (on NB) and launch_grad (on GB) of the same packed lanes L in
+// one launch of 2 grid workgroups; NB and GB share their descriptors.
+hipError_t launch_normal_grad(const ProbDesc &d0, const SwarmArrays &NB, const SwarmArrays &GB,
+                              int64_t grid, double *chi2, double *jtj, double *jtr, double *jrows,
+                              int64_t jstride, int64_t jld, double *grad, double *work,
+                              int64_t wld, int32_t mode, hipStream_t st, const Lanes &L);
 // Per-column Gauss-Newton step (on B.x) and acceptance, over B's layout.
 hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                            const double *jtj, const double *g, double gscale, const double *lam,

@@ -23,20 +23,47 @@ struct JacData {
     double cs, e1, e2, d1, d2, y, z;
 };
 
-__device__ __forceinline__ JacData jac_data(double mu, double mu1, const double s[6])
+// f(s) exactly as the propagation's right-hand side computes it (rhs: one
+// reciprocal R = 1/(D1 D2), D_j = r_j^2 sqrt(r_j^2), correctly rounded sqrt
+// and reciprocal; INRANGE selects the in-range sequences and returns their
+// certificate), and the Jacobian data at s from the same intermediates:
+// c1 = (1-mu) D2 R, c2 = mu D1 R, and, since D2 R = 1 / (r1^2 sqrt(r1^2)),
+// 1 / r1^2 = sqrt(r1^2) D2 R, so e1 = 3 c1 sqrt(r1^2) (D2 R) and likewise
+// e2, with no further square root or division.
+template <bool INRANGE>
+__device__ __forceinline__ bool rhs_jac(double mu, double mu1, const double s[6], double f[6],
+                                        JacData &J)
 {
-    JacData J;
-    J.y = s[1];
-    J.z = s[2];
-    J.d1 = s[0] + mu;
-    J.d2 = s[0] - mu1;
-    const double q = fma(J.z, J.z, J.y * J.y);
-    const double r1s = fma(J.d1, J.d1, q), r2s = fma(J.d2, J.d2, q);
-    const double c1 = mu1 / (r1s * sqrt(r1s)), c2 = mu / (r2s * sqrt(r2s));
-    J.cs = c1 + c2;
-    J.e1 = 3.0 * c1 / r1s;
-    J.e2 = 3.0 * c2 / r2s;
-    return J;
+    const double x = s[0], y = s[1], z = s[2], vx = s[3], vy = s[4];
+    const double d1 = x + mu;
+    const double d2 = x - mu1;
+    const double q = fma(z, z, y * y);
+    const double r1s = fma(d1, d1, q);
+    const double r2s = fma(d2, d2, q);
+    const double q1 = INRANGE ? sqrt_inrange(r1s) : sqrt(r1s);
+    const double q2 = INRANGE ? sqrt_inrange(r2s) : sqrt(r2s);
+    const double D1 = r1s * q1;
+    const double D2 = r2s * q2;
+    const double D = D1 * D2;
+    const double R = INRANGE ? div_inrange(1.0, D) : 1.0 / D;
+    const double i1 = D2 * R, i2 = D1 * R;
+    const double c1 = mu1 * i1;
+    const double c2 = mu * i2;
+    const double cs = c1 + c2;
+    f[0] = s[3];
+    f[1] = s[4];
+    f[2] = s[5];
+    f[3] = fma(-c2, d2, fma(-c1, d1, fma(2.0, vy, x)));
+    f[4] = fma(-cs, y, fma(-2.0, vx, y));
+    f[5] = -(cs * z);
+    J.cs = cs;
+    J.e1 = 3.0 * c1 * (q1 * i1);
+    J.e2 = 3.0 * c2 * (q2 * i2);
+    J.d1 = d1;
+    J.d2 = d2;
+    J.y = y;
+    J.z = z;
+    return !INRANGE || (D >= 0x1p-760 && D <= 0x1p1000);
 }
 
 // G u for the symmetric gravity block.
@@ -76,68 +103,81 @@ __device__ __forceinline__ void atmul(const JacData &J, const double v[6], doubl
     out[5] = v[2];
 }
 
-// Stage inputs of one RK4 step from X (the IEEE path, bit-identical to the
-// propagation), and optionally the stepped state.
-__device__ __forceinline__ void rk4_stages(double mu, double mu1, double h, double h2, double h6,
-                                           const double X[6], double s2[6], double s3[6],
-                                           double s4[6], double *Y)
+// Jacobian data at the four stage inputs X, s2, s3, s4 of one RK4 step of
+// size h from X, and optionally the stepped state Y. INRANGE as in rhs_jac;
+// the stage inputs are those of the propagation bit for bit wherever the
+// result is certified.
+template <bool INRANGE>
+__device__ __forceinline__ bool stages_jac(double mu, double mu1, double h, double h2, double h6,
+                                           const double X[6], JacData J[4], double *Y)
 {
-    double k[6], a[6];
-    rhs<false>(mu, mu1, X, k);
+    double k[6], a[6], s[6];
+    bool ok = rhs_jac<INRANGE>(mu, mu1, X, k, J[0]);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = k[d];
-        s2[d] = fma(h2, k[d], X[d]);
+        s[d] = fma(h2, k[d], X[d]);
     }
-    rhs<false>(mu, mu1, s2, k);
+    ok &= rhs_jac<INRANGE>(mu, mu1, s, k, J[1]);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fma(2.0, k[d], a[d]);
-        s3[d] = fma(h2, k[d], X[d]);
+        s[d] = fma(h2, k[d], X[d]);
     }
-    rhs<false>(mu, mu1, s3, k);
+    ok &= rhs_jac<INRANGE>(mu, mu1, s, k, J[2]);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         a[d] = fma(2.0, k[d], a[d]);
-        s4[d] = fma(h, k[d], X[d]);
+        s[d] = fma(h, k[d], X[d]);
     }
+    ok &= rhs_jac<INRANGE>(mu, mu1, s, k, J[3]);
     if (Y) {
-        rhs<false>(mu, mu1, s4, k);
 #pragma unroll
         for (int d = 0; d < 6; ++d) Y[d] = fma(h6, a[d] + k[d], X[d]);
     }
+    return ok;
+}
+
+// The same with the in-range sequences where the whole wave is certified,
+// else on the IEEE path (as rk4 does).
+__device__ __forceinline__ void stages_jac(double mu, double mu1, bool fast, double h, double h2,
+                                           double h6, const double X[6], JacData J[4], double *Y)
+{
+    bool ok = false;
+    if (fast) ok = stages_jac<true>(mu, mu1, h, h2, h6, X, J, Y);
+    if (!__all(ok)) stages_jac<false>(mu, mu1, h, h2, h6, X, J, Y);
 }
 
 // Reverse (transposed tangent) of one RK4 step taken from X: lam <- (dX'/dX)^T lam.
 // X' = X + h/6 (k1 + 2 k2 + 2 k3 + k4), s2 = X + h/2 k1, s3 = X + h/2 k2, s4 = X + h k3.
-__device__ __forceinline__ void rk4_vjp(double mu, double mu1, double h, const double X[6],
-                                        double lam[6])
+__device__ __forceinline__ void rk4_vjp(double mu, double mu1, bool fast, double h,
+                                        const double X[6], double lam[6])
 {
     const double h2 = 0.5 * h, h6 = h / 6.0;
-    double s2[6], s3[6], s4[6];
-    rk4_stages(mu, mu1, h, h2, h6, X, s2, s3, s4, nullptr);
+    JacData J[4];
+    stages_jac(mu, mu1, fast, h, h2, h6, X, J, nullptr);
     double kb[6], sb[6], xb[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) kb[d] = h6 * lam[d];
-    atmul(jac_data(mu, mu1, s4), kb, sb);
+    atmul(J[3], kb, sb);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         xb[d] = lam[d] + sb[d];
         kb[d] = fma(2.0 * h6, lam[d], h * sb[d]);
     }
-    atmul(jac_data(mu, mu1, s3), kb, sb);
+    atmul(J[2], kb, sb);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         xb[d] += sb[d];
         kb[d] = fma(2.0 * h6, lam[d], h2 * sb[d]);
     }
-    atmul(jac_data(mu, mu1, s2), kb, sb);
+    atmul(J[1], kb, sb);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         xb[d] += sb[d];
         kb[d] = fma(h6, lam[d], h2 * sb[d]);
     }
-    atmul(jac_data(mu, mu1, X), kb, sb);
+    atmul(J[0], kb, sb);
 #pragma unroll
     for (int d = 0; d < 6; ++d) lam[d] = xb[d] + sb[d];
 }
@@ -208,7 +248,7 @@ __device__ __forceinline__ void obs_cotangent(const KArgs &A, const double *row,
 #pragma unroll
         for (int d = 0; d < 3; ++d) sbar[d] = NAN;
     }
-    if (tau != 0.0) rk4_vjp(A.mu, A.mu1, tau, X, sbar);
+    if (tau != 0.0) rk4_vjp(A.mu, A.mu1, A.fast, tau, X, sbar);
 #pragma unroll
     for (int d = 0; d < 6; ++d) add[d] = sbar[d];
 }
@@ -223,13 +263,13 @@ constexpr int CKPT = ADJ_CKPT;   // steps between adjoint checkpoints (the host 
 // a [rows][6][wld] array): rows [0, nseg) checkpoints, [nseg, nseg + 64)
 // segment states. mode >= 0 overrides the cost mode.
 template <int BS, int PLACE>
-__global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L,
-                                             double *__restrict__ grad, double *__restrict__ work,
-                                             int64_t wld, int32_t mode)
+__device__ __forceinline__ void grad_body(int64_t blk, const ProbDesc &d0, const SwarmArrays &B,
+                                          const Lanes &L, double *__restrict__ grad,
+                                          double *__restrict__ work, int64_t wld, int32_t mode)
 {
     int64_t p, i;
     const ProbDesc *Dp;
-    if (!place<BS, PLACE>(d0, B, L, p, i, Dp)) return;
+    if (!place<BS, PLACE>(d0, B, L, blk, p, i, Dp)) return;
     const ProbDesc &D = *Dp;
     KArgs A = D.k;
     if (mode >= 0) A.mode = mode;
@@ -294,7 +334,7 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L
             double Xj[6];
 #pragma unroll
             for (int d = 0; d < 6; ++d) Xj[d] = valid ? seg[((int64_t)(j - a) * 6 + d) * wld + g] : X[d];
-            rk4_vjp(A.mu, A.mu1, A.h, Xj, lam);
+            rk4_vjp(A.mu, A.mu1, A.fast, A.h, Xj, lam);
             while (nk == j) {
                 double add[6];
                 obs_cotangent(A, A.tab + (int64_t)k * TAB_W, Xj, add);
@@ -312,18 +352,26 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L
     }
 }
 
+template <int BS, int PLACE>
+__global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L,
+                                             double *__restrict__ grad, double *__restrict__ work,
+                                             int64_t wld, int32_t mode)
+{
+    grad_body<BS, PLACE>(blockIdx.x, d0, B, L, grad, work, wld, mode);
+}
+
 // Forward tangent (6x6 state transition matrix of the discrete RK4 map) and
 // the Gauss-Newton normal equations of the whitened residuals
 // r = (da, db) / sigma: chi2 = sum r^2, N = J^T J (21 packed, row-major
 // upper triangle), jtr = J^T r.
-__device__ __forceinline__ void tangent_step(double mu, double mu1, double h, double X[6],
-                                             double Phi[36])
+__device__ __forceinline__ void tangent_step(double mu, double mu1, bool fast, double h,
+                                             double X[6], double Phi[36])
 {
     const double h2 = 0.5 * h, h6 = h / 6.0;
-    double s2[6], s3[6], s4[6], Y[6];
-    rk4_stages(mu, mu1, h, h2, h6, X, s2, s3, s4, Y);
-    const JacData J1 = jac_data(mu, mu1, X), J2 = jac_data(mu, mu1, s2);
-    const JacData J3 = jac_data(mu, mu1, s3), J4 = jac_data(mu, mu1, s4);
+    double Y[6];
+    JacData J[4];
+    stages_jac(mu, mu1, fast, h, h2, h6, X, J, Y);
+    const JacData &J1 = J[0], &J2 = J[1], &J3 = J[2], &J4 = J[3];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         double u[6], dk[6], acc[6], ds[6];
@@ -356,14 +404,15 @@ __device__ __forceinline__ void tangent_step(double mu, double mu1, double h, do
 }
 
 template <int BS, int PLACE>
-__global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes L,
-                                               double *__restrict__ chi2, double *__restrict__ jtj,
-                                               double *__restrict__ jtr, double *__restrict__ jrows,
-                                               int64_t jstride, int64_t jld)
+__device__ __forceinline__ void normal_body(int64_t blk, const ProbDesc &d0,
+                                            const SwarmArrays &B, const Lanes &L,
+                                            double *__restrict__ chi2, double *__restrict__ jtj,
+                                            double *__restrict__ jtr, double *__restrict__ jrows,
+                                            int64_t jstride, int64_t jld)
 {
     int64_t p, i;
     const ProbDesc *Dp;
-    if (!place<BS, PLACE>(d0, B, L, p, i, Dp)) return;
+    if (!place<BS, PLACE>(d0, B, L, blk, p, i, Dp)) return;
     const ProbDesc &D = *Dp;
     const KArgs &A = D.k;
     const bool valid = i < D.m;
@@ -392,7 +441,7 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes
 #pragma unroll
             for (int d = 0; d < 36; ++d) SP[d] = Phi[d];
             const double tau = row[TAB_TAU];
-            if (tau != 0.0) tangent_step(A.mu, A.mu1, tau, Sx, SP);
+            if (tau != 0.0) tangent_step(A.mu, A.mu1, A.fast, tau, Sx, SP);
             double da, db, ga[3], gb[3], dr = 0, gq[3] = {0, 0, 0};
             if (!residual_and_grad(row, Sx, da, db, ga, gb, ranged, dr, gq)) {
                 da = db = dr = NAN;
@@ -438,7 +487,7 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes
             ++k;
             nk = k < A.K ? A.ns[k] : -1;
         }
-        if (n < S) tangent_step(A.mu, A.mu1, A.h, X, Phi);
+        if (n < S) tangent_step(A.mu, A.mu1, A.fast, A.h, X, Phi);
     }
     if (valid) {
         const int64_t o = D.off + i;
@@ -448,6 +497,36 @@ __global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes
 #pragma unroll
         for (int d = 0; d < 6; ++d) jtr[d * B.ld + o] = gr[d];
     }
+}
+
+template <int BS, int PLACE>
+__global__ __launch_bounds__(BS) void k_normal(ProbDesc d0, SwarmArrays B, Lanes L,
+                                               double *__restrict__ chi2, double *__restrict__ jtj,
+                                               double *__restrict__ jtr, double *__restrict__ jrows,
+                                               int64_t jstride, int64_t jld)
+{
+    normal_body<BS, PLACE>(blockIdx.x, d0, B, L, chi2, jtj, jtr, jrows, jstride, jld);
+}
+
+// The normal equations (NB) and the adjoint gradient (GB) of the same packed
+// lanes in one launch: even workgroups take the tangent sweep of lane block
+// blockIdx.x / 2, odd ones the adjoint sweep of that block. When few lanes
+// are live, the two sweeps of a block then run side by side on different
+// SIMDs instead of one launch after the other.
+__global__ __launch_bounds__(64) void k_normal_grad(ProbDesc d0, SwarmArrays NB, SwarmArrays GB,
+                                                    Lanes L, double *__restrict__ chi2,
+                                                    double *__restrict__ jtj,
+                                                    double *__restrict__ jtr,
+                                                    double *__restrict__ jrows, int64_t jstride,
+                                                    int64_t jld, double *__restrict__ grad,
+                                                    double *__restrict__ work, int64_t wld,
+                                                    int32_t mode)
+{
+    const int64_t blk = blockIdx.x >> 1;
+    if (blockIdx.x & 1)
+        grad_body<64, PLACE_PACKED>(blk, d0, GB, L, grad, work, wld, mode);
+    else
+        normal_body<64, PLACE_PACKED>(blk, d0, NB, L, chi2, jtj, jtr, jrows, jstride, jld);
 }
 
 // Solve (N + l diag(N)) y = rhs by Cholesky, N = J^T J packed (row-major
@@ -920,6 +999,15 @@ hipError_t launch_normal(const ProbDesc &d0, const SwarmArrays &B, int bs, int64
     return hipGetLastError();
 }
 
+hipError_t launch_normal_grad(const ProbDesc &d0, const SwarmArrays &NB, const SwarmArrays &GB,
+                              int64_t grid, double *chi2, double *jtj, double *jtr, double *jrows,
+                              int64_t jstride, int64_t jld, double *grad, double *work,
+                              int64_t wld, int32_t mode, hipStream_t st, const Lanes &L)
+{
+    if (!L.pairs || NB.desc != GB.desc) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_normal_grad, dim3((unsigned)(2 * grid)), dim3(64), 0, st, d0, NB, GB, L, chi2, jtj, jtr, jrows, jstride, jld, grad, work, wld, mode);
+    return hipGetLastError();
+}
 
 hipError_t launch_gn_solve(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
                            const double *jtj, const double *g, double gscale, const double *lam,
