@@ -323,17 +323,58 @@ __device__ __forceinline__ void grad_body(int64_t blk, const ProbDesc &d0, const
         double Y[6];
 #pragma unroll
         for (int d = 0; d < 6; ++d) Y[d] = valid ? ck[((int64_t)sg * 6 + d) * wld + g] : X[d];
-        for (int32_t j = a; j < b; ++j) {
-            if (valid) {
+        // the segment's states, stored as they are reached: the in-range
+        // sequences with one certification vote for the segment (as
+        // rk4_steps), and the whole segment again on the IEEE path if a lane
+        // is not certified
+        bool ok = false;
+        if (A.fast) {
+            double Z[6];
 #pragma unroll
-                for (int d = 0; d < 6; ++d) seg[((int64_t)(j - a) * 6 + d) * wld + g] = Y[d];
+            for (int d = 0; d < 6; ++d) Z[d] = Y[d];
+            ok = true;
+#pragma unroll 2
+            for (int32_t j = a; j < b; ++j) {
+                if (valid) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) seg[((int64_t)(j - a) * 6 + d) * wld + g] = Z[d];
+                }
+                if (j + 1 < b) {
+                    double q[6];
+                    ok &= rk4_sum<true>(A.mu, A.mu1, A.h, A.h2, Z, q);
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) Z[d] = fma(A.h6, q[d], Z[d]);
+                }
             }
-            if (j + 1 < b) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
         }
+        if (!__all(ok)) {
+            for (int32_t j = a; j < b; ++j) {
+                if (valid) {
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) seg[((int64_t)(j - a) * 6 + d) * wld + g] = Y[d];
+                }
+                if (j + 1 < b) {
+                    double q[6];
+                    rk4_sum<false>(A.mu, A.mu1, A.h, A.h2, Y, q);
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) Y[d] = fma(A.h6, q[d], Y[d]);
+                }
+            }
+        }
+        // each step's state is loaded one step ahead, while the step after it
+        // is reversed, so the sweep does not wait for the load
+        double Xn[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Xn[d] = valid ? seg[((int64_t)(b - 1 - a) * 6 + d) * wld + g] : X[d];
         for (int32_t j = b - 1; j >= a; --j) {
             double Xj[6];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) Xj[d] = valid ? seg[((int64_t)(j - a) * 6 + d) * wld + g] : X[d];
+            for (int d = 0; d < 6; ++d) Xj[d] = Xn[d];
+            if (j > a) {
+#pragma unroll
+                for (int d = 0; d < 6; ++d)
+                    Xn[d] = valid ? seg[((int64_t)(j - 1 - a) * 6 + d) * wld + g] : X[d];
+            }
             rk4_vjp(A.mu, A.mu1, A.fast, A.h, Xj, lam);
             while (nk == j) {
                 double add[6];
@@ -364,6 +405,42 @@ __global__ __launch_bounds__(BS) void k_grad(ProbDesc d0, SwarmArrays B, Lanes L
 // the Gauss-Newton normal equations of the whitened residuals
 // r = (da, db) / sigma: chi2 = sum r^2, N = J^T J (21 packed, row-major
 // upper triangle), jtr = J^T r.
+// The gravity-plus-centrifugal block G as a matrix (its six distinct
+// entries), for products with the six columns of the tangent, where the
+// factored form would repeat the projections p_j . u for every column.
+struct GMat {
+    double g00, g01, g02, g11, g12, g22;
+};
+
+__device__ __forceinline__ GMat gmat(const JacData &J)
+{
+    const double t1 = J.e1 * J.d1, t2 = J.e2 * J.d2;
+    const double txy = t1 + t2, ey = J.e1 + J.e2, one_cs = 1.0 - J.cs;
+    const double eyy = ey * J.y;
+    GMat G;
+    G.g00 = fma(t1, J.d1, fma(t2, J.d2, one_cs));
+    G.g01 = txy * J.y;
+    G.g02 = txy * J.z;
+    G.g11 = fma(eyy, J.y, one_cs);
+    G.g12 = eyy * J.z;
+    G.g22 = fma(ey * J.z, J.z, -J.cs);
+    return G;
+}
+
+// A(s) u with G given as a matrix.
+__device__ __forceinline__ void amul(const GMat &G, const double u[6], double out[6])
+{
+    const double g0 = fma(G.g00, u[0], fma(G.g01, u[1], G.g02 * u[2]));
+    const double g1 = fma(G.g01, u[0], fma(G.g11, u[1], G.g12 * u[2]));
+    const double g2 = fma(G.g02, u[0], fma(G.g12, u[1], G.g22 * u[2]));
+    out[0] = u[3];
+    out[1] = u[4];
+    out[2] = u[5];
+    out[3] = fma(2.0, u[4], g0);
+    out[4] = fma(-2.0, u[3], g1);
+    out[5] = g2;
+}
+
 __device__ __forceinline__ void tangent_step(double mu, double mu1, bool fast, double h,
                                              double X[6], double Phi[36])
 {
@@ -371,7 +448,7 @@ __device__ __forceinline__ void tangent_step(double mu, double mu1, bool fast, d
     double Y[6];
     JacData J[4];
     stages_jac(mu, mu1, fast, h, h2, h6, X, J, Y);
-    const JacData &J1 = J[0], &J2 = J[1], &J3 = J[2], &J4 = J[3];
+    const GMat J1 = gmat(J[0]), J2 = gmat(J[1]), J3 = gmat(J[2]), J4 = gmat(J[3]);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         double u[6], dk[6], acc[6], ds[6];
@@ -682,28 +759,30 @@ __global__ __launch_bounds__(64) void k_geo(const ProbDesc *__restrict__ descs,
         Y[d] = fma(hd, v[d], x[d * ld + c]);
         gy[d] = 0.0;
     }
-    const int32_t S = A.ns[A.K - 1];
-    int32_t kk = 0;
-    for (int32_t st = 0; st <= S; ++st) {
-        while (kk < A.K && A.ns[kk] == st) {
-            const double *row = A.tab + (int64_t)kk * TAB_W;
-            double Sy[6];
-#pragma unroll
-            for (int d = 0; d < 6; ++d) Sy[d] = Y[d];
-            const double tau = row[TAB_TAU];
-            if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sy);
-            double ea, eb, fa[3], fb[3], er = 0, fq[3] = {0, 0, 0};
-            if (!residual_and_grad(row, Sy, ea, eb, fa, fb, ranged, er, fq)) return;   // keeps x + v
-            const double ra = ea * is, rb = eb * is, rr = er * isr;
-            const double *q = rows + (int64_t)kk * R * 6 * jld;
-#pragma unroll
-            for (int cc = 0; cc < 6; ++cc) {
-                gy[cc] = fma(q[cc * jld], ra, fma(q[(6 + cc) * jld], rb, gy[cc]));
-                if (ranged) gy[cc] = fma(q[(12 + cc) * jld], rr, gy[cc]);
-            }
-            ++kk;
+    // the steps between observations run as the fitness kernel's do (one
+    // certification vote per interval)
+    int32_t step = 0;
+    for (int32_t kk = 0; kk < A.K; ++kk) {
+        const int32_t target = A.ns[kk];
+        if (target > step) {
+            rk4_steps(A, target - step, Y);
+            step = target;
         }
-        if (st < S) rk4(A.mu, A.mu1, A.fast, A.h, A.h2, A.h6, Y);
+        const double *row = A.tab + (int64_t)kk * TAB_W;
+        double Sy[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) Sy[d] = Y[d];
+        const double tau = row[TAB_TAU];
+        if (tau != 0.0) rk4(A.mu, A.mu1, A.fast, tau, 0.5 * tau, tau / 6.0, Sy);
+        double ea, eb, fa[3], fb[3], er = 0, fq[3] = {0, 0, 0};
+        if (!residual_and_grad(row, Sy, ea, eb, fa, fb, ranged, er, fq)) return;   // keeps x + v
+        const double ra = ea * is, rb = eb * is, rr = er * isr;
+        const double *q = rows + (int64_t)kk * R * 6 * jld;
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) {
+            gy[cc] = fma(q[cc * jld], ra, fma(q[(6 + cc) * jld], rb, gy[cc]));
+            if (ranged) gy[cc] = fma(q[(12 + cc) * jld], rr, gy[cc]);
+        }
     }
     // J^T r_vv = (2 / hd) ((gy - J^T r) / hd - N v)
     double Nv[6] = {0, 0, 0, 0, 0, 0};

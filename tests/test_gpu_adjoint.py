@@ -203,6 +203,45 @@ def test_normal_equations_random_problems(torch_dev, seed):
         assert np.max(np.abs(jtr[:, i] - J.T @ r)) <= 1e-9 * np.max(np.abs(J.T @ r)), (seed, i)
 
 
+def test_sensitivities_beside_an_uncertified_lane(torch_dev):
+    """A particle far outside the certified range (r1^3 r2^3 overflows, so
+    D1 D2 is above 2^1000) puts its wave on the IEEE path for every step:
+    the stage Jacobians of the tangent and adjoint steps and the adjoint's
+    segment recomputation are then all redone there. The ordinary particles
+    of that wave must still get the oracle's cost, gradient and normal
+    equations (same bars as above), and the far particle the forward cost of
+    iod_eval_swarm."""
+    torch, dev = torch_dev
+    wl = W.tiny(2, K=8, T=0.8)
+    P, h = make(wl, mode=1)
+    xs = particles(wl, n=20, seed=7)
+    far = 5
+    xs[far] = [3e54, 0.0, 0.0, 0.0, 0.0, 0.0]
+    x = cols(torch, dev, xs)
+    ld = x.shape[1]
+    chi2 = torch.zeros(ld, dtype=torch.float64, device=dev)
+    jtj = torch.zeros((21, ld), dtype=torch.float64, device=dev)
+    jtr = torch.zeros((6, ld), dtype=torch.float64, device=dev)
+    iod.iod_normal_eq(h, x, len(xs), chi2, jtj, jtr)
+    cost, g = gpu_grad(torch, dev, h, xs)
+    ref_cost = torch.zeros(ld, dtype=torch.float64, device=dev)
+    iod.iod_eval_swarm(h, x, len(xs), ref_cost)
+    torch.cuda.synchronize()
+    assert np.array_equal(cost, ref_cost.cpu().numpy()[:len(xs)], equal_nan=True)
+    chi2, jtj, jtr = chi2.cpu().numpy(), jtj.cpu().numpy(), jtr.cpu().numpy()
+    iu = np.triu_indices(6)
+    for i, xi in enumerate(xs):
+        if i == far:
+            continue
+        gs, _ = oracle.grad(P, xi)
+        assert np.max(np.abs(g[i] - gs)) <= 1e-9 * np.max(np.abs(gs)), i
+        r, J = oracle.residuals(P, xi, jacobian=True)
+        assert abs(chi2[i] - r @ r) <= 1e-11 * (r @ r), i
+        N = J.T @ J
+        assert np.max(np.abs(jtj[:, i] - N[iu])) <= 1e-9 * np.max(np.abs(N)), i
+        assert np.max(np.abs(jtr[:, i] - J.T @ r)) <= 1e-9 * np.max(np.abs(J.T @ r)), i
+
+
 def lsq_reference(P, x0):
     from scipy.optimize import least_squares
     res = least_squares(lambda v: oracle.residuals(P, v), x0,

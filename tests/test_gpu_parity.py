@@ -150,7 +150,7 @@ def test_eval_nonfinite_cases(torch_dev):
         [1 - wl.mu, 0, 0, 0, 0, 0],                        # on the smaller primary
         [1e300, 0, 0, 0, 0, 0],
         [3e54, 0, 0, 0, 0, 0],                             # r1^3 r2^3 overflows
-        [1e20, 1e20, 0, 0, 0, 0],                          # outside the certified range
+        [1e20, 1e20, 0, 0, 0, 0],                          # large, inside the certified range
         [-wl.mu + 1e-160, 0, 0, 0, 0, 0],                  # r1^2 below the sqrt range
         [1 - wl.mu + 1e-120, 1e-130, 0, 0, 1.0, 0],        # next to the smaller primary
         wl.truth,
