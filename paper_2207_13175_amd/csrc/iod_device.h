@@ -587,32 +587,6 @@ __device__ __forceinline__ const ProbDesc &locate(const ProbDesc &d0, const Swar
     return B.desc[p];
 }
 
-// Thread placement of the sensitivity kernels: SINGLE and BATCH as locate
-// (one problem per workgroup); PACKED, one (problem, particle) pair per
-// thread from L, so that a wave can hold the candidates of several problems.
-// Returns false for a thread with nothing to do (past the lanes, or its
-// problem inactive; uniform over the workgroup unless PACKED). blk is the
-// PACKED workgroup's index among the lanes' workgroups.
-enum { PLACE_SINGLE = 0, PLACE_BATCH = 1, PLACE_PACKED = 2 };
-
-template <int BS, int PLACE>
-__device__ __forceinline__ bool place(const ProbDesc &d0, const SwarmArrays &B, const Lanes &L,
-                                      int64_t blk, int64_t &p, int64_t &i, const ProbDesc *&D)
-{
-    if (PLACE == PLACE_PACKED) {
-        const int64_t q = blk * BS + threadIdx.x;
-        if (q >= (L.count ? *L.count : L.n)) return false;
-        p = L.pairs[2 * q];
-        i = L.pairs[2 * q + 1];
-        D = &B.desc[p];
-    } else {
-        int64_t tile;
-        D = &locate<PLACE == PLACE_SINGLE>(d0, B, p, tile);
-        i = tile * BS + threadIdx.x;
-    }
-    return !(B.active && !B.active[p]);
-}
-
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
