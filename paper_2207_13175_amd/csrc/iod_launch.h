@@ -57,9 +57,8 @@ hipError_t launch_reeval64(const SwarmArrays &B, const int32_t *cand, int32_t to
 // overrides the cost mode. B.cost receives the cost, grad [6][B.ld] its
 // gradient.
 hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st,
-                       const Lanes &L = Lanes());
-// With L.pairs set, both launches below take the packed placement (one
+                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st);
+// With L.pairs set, the launches below take the packed placement (one
 // (problem, particle) pair per thread, workgroups of 64, grid covering L.n).
 // chi2 [ld], jtj [21][ld], jtr [6][ld] of the whitened residuals. With
 // jrows, also the rows of J: observation k's residual r (R = 2, or 3 with

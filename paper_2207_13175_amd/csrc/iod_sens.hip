@@ -1075,13 +1075,10 @@ __global__ __launch_bounds__(BS) void k_gn_accept(ProbDesc d0, SwarmArrays B,
 // ---------------------------------------------------------------------------
 
 hipError_t launch_grad(const ProbDesc &d0, const SwarmArrays &B, int bs, int64_t grid,
-                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st,
-                       const Lanes &L)
+                       double *grad, double *work, int64_t wld, int32_t mode, hipStream_t st)
 {
-    if (L.pairs) {
-        if (bs != 64) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_grad<64, PLACE_PACKED>), dim3((unsigned)grid), dim3(64), 0, st, d0, B, L, grad, work, wld, mode);
-    } else if (B.desc == nullptr) {
+    const Lanes L;
+    if (B.desc == nullptr) {
         IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_grad<BS_, PLACE_SINGLE>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, grad, work, wld, mode));
     } else {
         IOD_DISPATCH_BS(bs, hipLaunchKernelGGL((k_grad<BS_, PLACE_BATCH>), dim3((unsigned)grid), dim3(BS_), 0, st, d0, B, L, grad, work, wld, mode));
