@@ -7,7 +7,7 @@ entry paddings (iter_pad in iod_mixed.hip) are chosen to land at 8 mod 32.
 An edit to that file or to the device code it includes moves the loops;
 this test then names each instance that left the fast offsets, so that its
 padding can be retuned. It compiles the file's device code (hipcc for
-gfx950, no GPU needed) and reads this build's own disassembly."""
+gfx950, no GPU needed) and reads the disassembly of that compiled code."""
 import os
 import re
 import shutil
