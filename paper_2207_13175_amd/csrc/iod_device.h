@@ -151,7 +151,10 @@ __device__ __forceinline__ void rk4(double mu, double mu1, bool fast, double h, 
 // the IEEE path. Either way the result is that of correctly rounded sqrt and
 // division, bit for bit, as with a vote per step; without a branch between
 // steps the scheduler can overlap one step's distance chains with the end
-// of the previous step.
+// of the previous step. U steps per loop trip: a wave that has its SIMD to
+// itself gains from a longer trip, while waves that share one hide each
+// other's latency anyway (the callers choose).
+template <int U = 2>
 __device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6])
 {
     if (A.fast) {
@@ -159,7 +162,7 @@ __device__ __forceinline__ void rk4_steps(const KArgs &A, int32_t n, double X[6]
 #pragma unroll
         for (int d = 0; d < 6; ++d) X0[d] = X[d];
         bool ok = true;
-#pragma unroll 2
+#pragma unroll U
         for (int32_t j = 0; j < n; ++j) {
             double a[6];
             ok &= rk4_sum<true>(A.mu, A.mu1, A.h, A.h2, X, a);
@@ -202,7 +205,7 @@ struct WaveScope {
 // when the time is off the grid) to `obs(row, S)`. Every thread of the scope
 // (the workgroup, or the wave) must call this: it stages the table through
 // LDS in chunks.
-template <class Scope = BlockScope, class Obs>
+template <class Scope = BlockScope, int U = 2, class Obs>
 __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, int32_t *lds_ns,
                                      Obs &obs)
 {
@@ -218,7 +221,7 @@ __device__ __forceinline__ void walk(const KArgs &A, double X[6], double *lds, i
             const double *row = lds + kk * TAB_W;
             const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
             if (target > step) {
-                rk4_steps(A, target - step, X);
+                rk4_steps<U>(A, target - step, X);
                 step = target;
             }
             const double tau = row[TAB_TAU];
@@ -280,7 +283,7 @@ struct CostAcc {
     }
 };
 
-template <class Scope = BlockScope>
+template <class Scope = BlockScope, int U = 2>
 __device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], double *lds,
                                             int32_t *lds_ns)
 {
@@ -288,7 +291,7 @@ __device__ __forceinline__ double eval_cost(const KArgs &A, const double x0[6], 
 #pragma unroll
     for (int d = 0; d < 6; ++d) X[d] = x0[d];
     CostAcc acc{0.0, A.w, A.mode, A.wr};
-    walk<Scope>(A, X, lds, lds_ns, acc);
+    walk<Scope, U>(A, X, lds, lds_ns, acc);
     return acc.J;
 }
 

@@ -215,6 +215,12 @@ __global__ __launch_bounds__(BS) void k_eval(ProbDesc d0, SwarmArrays B)
     if (valid) B.cost[D.off + i] = J;
 }
 
+// RK4 steps per loop trip of the swarm kernels (rk4_steps): a single
+// problem's swarm kernels run one wave per SIMD at the workload sizes, where
+// 8 steps per trip measured 1.3% faster than 2; the batched ones share each
+// SIMD between waves, and keep 2 (8 measured 0.4% slower there).
+constexpr int steps_per_trip(bool single) { return single ? 8 : 2; }
+
 // Algorithm 1 initialisation.
 template <int BS, bool SINGLE>
 __global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(BS) void k_swarm_init(ProbDesc d0, SwarmArrays B)
     const int64_t j = valid ? i : D.m - 1;
     double X[6];
     init_state(D, j, X);
-    const double J = eval_cost(D.k, X, lds, lds_ns);
+    const double J = eval_cost<BlockScope, steps_per_trip(SINGLE)>(D.k, X, lds, lds_ns);
     const int64_t ld = B.ld, g = D.off + i;
     if (valid) {
 #pragma unroll
@@ -300,7 +306,7 @@ __device__ __forceinline__ void swarm_iter(const ProbDesc &d0, const SwarmArrays
     double jp = B.jp[gj];
     double J;
     if (n >= 2)
-        J = eval_cost(D.k, X, lds, lds_ns);
+        J = eval_cost<BlockScope, steps_per_trip(SINGLE)>(D.k, X, lds, lds_ns);
     else
         J = B.cost[gj];
     const bool better = cost_key(J) < cost_key(jp);
