@@ -229,7 +229,11 @@ __device__ __forceinline__ void walk32_abs(const KArgs &A, float X[6], float C[6
 // while the current one is in use, so the global-memory latency is not
 // paid at the hand-over. A chunk is fetched only if it starts before the
 // last step, which keeps every read inside the table's CST_CHUNK padding
-// rows.
+// rows. The steps up to the next observation or chunk end run as a loop of
+// their own, two per trip, so that the scheduler can start a step's
+// distance chains before the previous step's last stage is done (at one
+// wave per SIMD the single large swarm's evaluation went from 2.39 to
+// 1.93 ms with it, the same bits).
 template <int BS, class Obs>
 __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6], double *lds,
                                            int32_t *lds_ns, float *lds_c, Obs &obs)
@@ -256,7 +260,7 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
         for (int32_t kk = 0; kk < nk; ++kk) {
             const double *row = lds + kk * TAB_W;
             const int32_t target = __builtin_amdgcn_readfirstlane(lds_ns[kk]);
-            for (; step < target; ++step) {
+            while (step < target) {
                 if (step >= c0 + CST_CHUNK) {
                     c0 = step;
                     __syncthreads();
@@ -269,7 +273,10 @@ __device__ __forceinline__ void walk32_rel(const KArgs &A, float D[6], float C[6
                     }
                     __syncthreads();
                 }
-                rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, h6lo, D, C);
+                const int32_t stop = min(target, c0 + CST_CHUNK);
+#pragma unroll 2
+                for (; step < stop; ++step)
+                    rk4_32_rel(lds_c + (step - c0) * CST_STEP, h, h2, h6, h6lo, D, C);
             }
             const float tau = (float)row[TAB_TAU];
             float S[6], SC[6];
