@@ -401,12 +401,13 @@ double iod_batch_last_iter_ms(const iod_batch *b);
  *     chief + offset and at the chief, in a cancellation-free form, so
  *     rounding errors scale with the offset (1e-3 to 1e-2 LU), not with the
  *     state (~1 LU); the line of sight at an observation is the offset
- *     itself. Position errors up to ~1.5e-8 LU after 4,000 steps of 5e-4 TU.
+ *     itself. Position errors ~2e-9 LU after 4,000 steps of 5e-4 TU (~4e-8
+ *     with the chief 0.03 LU from the second primary).
  *   IOD_FP32_ABSOLUTE: the particle's own state is propagated (1/r^3 from
  *     the hardware reciprocal square root) and the chief position is
- *     subtracted at each observation. 70% of the instructions per step and
- *     no table, position errors up to ~1.5e-7 LU: a ranking for throughput
- *     when a refinement follows.
+ *     subtracted at each observation. Two thirds of the instructions per
+ *     step and no table, position errors ~1.5e-7 LU (~8e-7 near the second
+ *     primary): a ranking for throughput when a refinement follows.
  * Both accumulate the RK4 increment with Kahan compensation. Host only.
  * Errors: IOD_EINVAL (unknown mode). */
 #define IOD_FP32_RELATIVE 0
