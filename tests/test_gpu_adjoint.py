@@ -203,6 +203,38 @@ def test_normal_equations_random_problems(torch_dev, seed):
         assert np.max(np.abs(jtr[:, i] - J.T @ r)) <= 1e-9 * np.max(np.abs(J.T @ r)), (seed, i)
 
 
+@pytest.mark.parametrize("case", ["c0", "offgrid"])
+def test_tangent_sweep_propagates_the_evaluated_states(torch_dev, case):
+    """The tangent sweep re-derives each RK4 stage (to take the Jacobian at
+    it) and steps the state itself; that state must be the evaluation's bit
+    for bit. Its chi2 is compared with iod_eval_swarm's least-squares cost at
+    particles near the truth, where residuals sit at the noise level and a
+    state one ulp off would move the cost by ~1e-8 relative; with equal
+    states the two differ only in how the weight is applied (a few ulps)."""
+    torch, dev = torch_dev
+    if case == "c0":
+        wl, t = W.c0(0), None
+    else:
+        wl = W.tiny(1, K=5, T=0.3)
+        t = [0.0123, 0.0127, 0.1, 0.2004, 0.2501]
+    P, h = make(wl, 1, t)
+    rng = np.random.default_rng(11)
+    xs = wl.truth + rng.normal(0.0, 1e-7, (24, 6))
+    x = cols(torch, dev, xs)
+    ld = x.shape[1]
+    chi2 = torch.zeros(ld, dtype=torch.float64, device=dev)
+    jtj = torch.zeros((21, ld), dtype=torch.float64, device=dev)
+    jtr = torch.zeros((6, ld), dtype=torch.float64, device=dev)
+    iod.iod_normal_eq(h, x, len(xs), chi2, jtj, jtr)
+    cost = torch.zeros(ld, dtype=torch.float64, device=dev)
+    iod.iod_eval_swarm(h, x, len(xs), cost)
+    torch.cuda.synchronize()
+    a, b = chi2.cpu().numpy()[:len(xs)], cost.cpu().numpy()[:len(xs)]
+    rel = np.abs(a - b) / b
+    print(f"{case}: chi2 of the tangent sweep vs the evaluated cost, max rel {rel.max():.2e}")
+    assert np.all(rel <= 1e-13), rel
+
+
 def test_sensitivities_beside_an_uncertified_lane(torch_dev):
     """A particle far outside the certified range (r1^3 r2^3 overflows, so
     D1 D2 is above 2^1000) puts its wave on the IEEE path for every step:
